@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Tokenizer round-trip benchmark on one MI355X.
+
+A step is one pass of the whole hot path over one batch: encode (causal
+conv3d stack), FSQ and token mask (fused), decode, on 4 clips of 17 frames at
+1280x720 (uint8 in, float32 reconstruction out), inputs resident in HBM.
+Prints one JSON line with frames/s, per-kernel times, the roofline of the
+dominant kernel, the FP32 path on the same GPU and the FP64 CPU oracle on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tokenizer encode+decode frames/s at 720p, BF16 vs FP32, ≤0.5 dB PSNR vs oracle"
+BF16_PEAK_TFLOPS = 2500.0
+F32_PEAK_TFLOPS = 157.3
+# FLOPs per output position of each conv (2 * 27 * Cin * Cout, 1x1x1: 2 * Cin * Cout) and the level it runs at.
+CONV_FLOPS = {
+    "enc.conv_in": (2 * 27 * 3 * 64, 0), "enc.rb1.a": (2 * 27 * 64 * 64, 0), "enc.rb1.b": (2 * 27 * 64 * 64, 0),
+    "enc.rb2.a": (2 * 27 * 64 * 64, 0), "enc.rb2.b": (2 * 27 * 64 * 64, 0), "enc.down1": (2 * 27 * 64 * 128, 1),
+    "enc.down2": (2 * 27 * 128 * 128, 2), "enc.proj+fsq+drop": (2 * 128 * 6, 2), "dec.proj_in": (2 * 6 * 128, 2),
+    "dec.up2": (2 * 27 * 128 * 128, 1), "dec.up1": (2 * 27 * 128 * 64, 0), "dec.rb1.a": (2 * 27 * 64 * 64, 0),
+    "dec.rb1.b": (2 * 27 * 64 * 64, 0), "dec.rb2.a": (2 * 27 * 64 * 64, 0), "dec.rb2.b": (2 * 27 * 64 * 64, 0),
+    "dec.conv_out": (2 * 27 * 64 * 3, 0)}
+RB_CONVS = [k for k in CONV_FLOPS if ".rb" in k]
+
+
+def level_positions(N, T, H, W):
+    T1, T2 = (T - 1) // 2 + 1, (T - 1) // 4 + 1
+    return {0: N * T * H * W, 1: N * T1 * (H // 2) * (W // 2), 2: N * T2 * (H // 4) * (W // 4)}
+
+
+def algorithmic_flops(N, T, H, W):
+    pos = level_positions(N, T, H, W)
+    return sum(f * pos[lv] for f, lv in CONV_FLOPS.values())
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return os.cpu_count() or 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--frames", type=int, default=17)
+    ap.add_argument("--height", type=int, default=720)
+    ap.add_argument("--width", type=int, default=1280)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--cpu-crop", type=str, default="180x320", help="HxW crop of clip 0 frame 0 for the oracle leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (clips shard across GPUs "
+              "with no exchange; run one process per GPU and add the frames/s).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2602_03529_amd import tok
+
+    N, T, H, W = args.batch, args.frames, args.height, args.width
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: generating %dx%dx%dx%d synthetic clips" % (N, T, H, W), file=sys.stderr, flush=True)
+    x = torch.from_numpy(synth.make_batch(list(range(N)), T, H, W)).to(dev)
+    wflat = synth.flatten_weights(synth.make_weights(1))
+    T2, H2, W2 = tok.latent_shape(T, H, W)
+
+    def make_runner(prec):
+        m = tok.TokModel(wflat, prec)
+        ws = torch.empty(m.workspace_size(N, T, H, W), dtype=torch.uint8, device=dev)
+        bufs = dict(codes=torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=dev),
+                    idx=torch.empty((N, T2, H2, W2), dtype=torch.int32, device=dev))
+        xh = torch.empty((N, T, H, W, 3), dtype=torch.float32, device=dev)
+
+        def step():
+            out = m.encode(x, z=False, keep=False, out=bufs, ws=ws)
+            m.decode(out["codes"], out=xh, ws=ws)
+        return m, step, xh
+
+    def timed(step, steps, model=None):
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        prof = tok.Profile(model) if model is not None else None
+        if prof:
+            prof.__enter__()
+        e0.record(s)
+        for _ in range(steps):
+            step()
+        e1.record(s)
+        torch.cuda.synchronize()
+        if prof:
+            prof.__exit__(None, None, None)
+        return e0.elapsed_time(e1) / steps, prof
+
+    # ---- BF16 headline ----------------------------------------------------
+    mb, step_b, xh_b = make_runner("bf16")
+    for _ in range(args.warmup):
+        step_b()
+    torch.cuda.synchronize()
+    print("bench: bf16 warmup done", file=sys.stderr, flush=True)
+    ms_b, prof_b = timed(step_b, args.steps, mb)
+    frames = N * T
+    value = frames / (ms_b / 1e3)
+    print("bench: bf16 %.2f ms/step" % ms_b, file=sys.stderr, flush=True)
+
+    pos = level_positions(N, T, H, W)
+    per_kernel = {}
+    for name, ms in prof_b.ms.items():
+        c = prof_b.count[name]
+        if c == 0:
+            continue
+        d = dict(avg_ms=ms / c, launches_per_step=c / args.steps)
+        if name in CONV_FLOPS:
+            f, lv = CONV_FLOPS[name]
+            d["tflops"] = f * pos[lv] / (ms / c / 1e3) / 1e12
+        per_kernel[name] = d
+    # dominant kernel: the level-0 64->64 residual-block conv (8 launches per step, same shape)
+    rb_ms = sum(prof_b.ms[k] for k in RB_CONVS)
+    rb_n = sum(prof_b.count[k] for k in RB_CONVS)
+    rb_avg_ms = rb_ms / rb_n
+    rb_flops = CONV_FLOPS["enc.rb1.a"][0] * pos[0]
+    achieved = rb_flops / (rb_avg_ms / 1e3) / 1e12
+    roofline = dict(kernel="level-0 residual-block conv 64->64 (bf16 MFMA, GN+SiLU prologue)", bound="mfma",
+                    achieved=round(achieved, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / BF16_PEAK_TFLOPS, 4), traffic=None,
+                    avg_launch_ms=round(rb_avg_ms, 4), flops_per_launch=rb_flops,
+                    share_of_step=round(rb_ms / args.steps / ms_b, 3))
+    total_flops = algorithmic_flops(N, T, H, W)
+
+    # ---- FP32 path on the same GPU -----------------------------------------
+    fp32 = None
+    if args.fp32_steps > 0:
+        del xh_b
+        mf, step_f, _ = make_runner("f32")
+        step_f()
+        torch.cuda.synchronize()
+        ms_f, _ = timed(step_f, args.fp32_steps)
+        fp32 = dict(value=round(frames / (ms_f / 1e3), 3), ms_per_step=round(ms_f, 2),
+                    tflops=round(total_flops / (ms_f / 1e3) / 1e12, 2))
+        print("bench: f32 %.2f ms/step" % ms_f, file=sys.stderr, flush=True)
+        mf.close()
+
+    # ---- CPU oracle on a bounded sample + PSNR criterion on that sample ----
+    cpu = None
+    psnr = None
+    if not args.no_cpu_baseline:
+        from oracle import tokenizer as O
+        hc, wc = (int(v) for v in args.cpu_crop.split("x"))
+        u8 = x[0:1, 0:1].cpu().numpy()
+        h0, w0 = ((H - hc) // 2) // 4 * 4, ((W - wc) // 2) // 4 * 4
+        crop = np.ascontiguousarray(u8[:, :, h0:h0 + hc, w0:w0 + wc])
+        p64 = {k: v.astype(np.float64) for k, v in synth.make_weights(1).items()}
+        t0 = time.perf_counter()
+        ref = O.roundtrip(crop, p64)
+        dt = time.perf_counter() - t0
+        area = (hc * wc) / float(H * W)
+        cpu = dict(value=round(area / dt, 6), unit="frames/s", cores=blas_threads(), kind="oracle",
+                   sample="clip 0 frame 0, %dx%d centre crop, FP64 round trip in %.1f s; frames/s scaled by the "
+                          "crop's share of a %dx%d frame" % (hc, wc, dt, W, H))
+        xc = torch.from_numpy(crop).to(dev)
+        out = mb.encode(xc)
+        xg = mb.decode(out["codes"]).cpu().numpy()
+        src = O.pixels_to_input(crop)
+        psnr = dict(sample="clip 0 frame 0 %dx%d crop" % (hc, wc),
+                    gpu_bf16_vs_oracle_db=round(O.psnr(xg, ref["xhat"]), 3),
+                    gpu_bf16_vs_source_db=round(O.psnr(xg, src), 3),
+                    oracle_vs_source_db=round(O.psnr(ref["xhat"], src), 3),
+                    idx_agreement=round(float((out["idx"].cpu().numpy() == ref["idx"]).mean()), 4))
+        psnr["criterion_abs_diff_db"] = round(abs(psnr["gpu_bf16_vs_source_db"] - psnr["oracle_vs_source_db"]), 4)
+        psnr["pass"] = bool(psnr["criterion_abs_diff_db"] <= 0.5)
+
+    line = dict(metric=METRIC, value=round(value, 3), unit="frames/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(ms_b, 3), higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="bf16", data="synthetic",
+                config=dict(workload="tokenizer round trip (encode + FSQ/drop + decode), %d clips x %d frames "
+                                     "x %dx%d, seeded stand-in weights" % (N, T, W, H),
+                            batch=N, frames=T, height=H, width=W, precision="bf16"),
+                algorithmic_tflops_per_step=round(total_flops / 1e12, 3),
+                achieved_tflops=round(total_flops / (ms_b / 1e3) / 1e12, 2),
+                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, per_kernel=per_kernel)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

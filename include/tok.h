@@ -1,0 +1,168 @@
+/*
+ * tok.h - C ABI of the MI355X video-tokenizer library (libtok.so).
+ *
+ * The library implements the data-parallel hot path of the generative codec
+ * of arXiv 2602.03529 ("Morphe"): the visual tokenizer's encoder f_phi,
+ * finite scalar quantisation of the latent, token dropping with zero fill,
+ * and the decoder g_theta (Sec. 2.4 defines f_phi / g_theta; Sec. 4.3 the
+ * per-frame token matrices; Sec. 6.2 the zero fill of dropped and lost
+ * tokens).  The paper does not publish the tokenizer's layer list, so the
+ * network is a seeded stand-in of the same kind (causal 3-D convolutions,
+ * GroupNorm+SiLU residual blocks, stride-2 down/up-sampling, FSQ):
+ *
+ *   encode: u8 -> x/127.5-1 -> conv 3->64 -> RB(64) x2 -> conv 64->128 /2
+ *           -> conv 128->128 /2 -> 1x1 128->6 = z
+ *   FSQ   : levels [8,8,8,5,5,5]: b = tanh(z+s)h - o, q = rint(b),
+ *           codes = q / floor(L/2), idx = sum (q + floor(L/2)) * [1,8,64,512,2560,12800]
+ *   drop  : codes *= keep (all 6 channels of a dropped token become 0)
+ *   decode: 1x1 6->128 -> up x2 + conv 128->128 -> up x2 + conv 128->64
+ *           -> RB(64) x2 -> conv 64->3 = x_hat
+ *   RB(x) = x + conv(SiLU(GN(conv(SiLU(GN(x)))))), GN = GroupNorm(32) per frame.
+ * All 3x3x3 convolutions are causal in time (two copies of frame 0 in front)
+ * and zero-padded in space; the first latent frame depends on frame 0 only.
+ *
+ * Conventions
+ *  - Every tensor argument is a DEVICE pointer unless marked "host".  The
+ *    caller owns every tensor and the workspace; the library owns only the
+ *    packed weights inside a tok_model.  No call allocates device memory
+ *    except tok_model_create.
+ *  - Pixel and output tensors are dense NDHWC: x is uint8 (N,T,H,W,3),
+ *    x_hat is float32 (N,T,H,W,3).  Latent tensors are dense float32
+ *    (N,T2,H2,W2,6); idx is int32 (N,T2,H2,W2); keep is uint8 (N,T2,H2,W2).
+ *    T2 = (T-1)/4 + 1, H2 = H/4, W2 = W/4.
+ *  - Shapes: N >= 1, T >= 1 with T % 4 == 1, H and W positive multiples of 4.
+ *    Violations return TOK_ESHAPE before anything is launched.
+ *  - Every compute call is asynchronous on the given HIP stream; nothing
+ *    synchronises the host.  Kernel faults surface as TOK_EDEVICE from a
+ *    later call or from the caller's own synchronisation.
+ *  - Results are deterministic (no floating-point atomics) and
+ *    batch-invariant: a clip's outputs do not depend on the other clips of
+ *    the batch.
+ *  - Errors: every call returns a tok_status; nothing throws across the
+ *    ABI.  tok_last_error() returns a thread-local description of the last
+ *    failure.
+ */
+#ifndef TOK_H
+#define TOK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TOK_OK = 0,
+  TOK_EINVAL = -1,        /* null pointer or invalid enum / argument */
+  TOK_ESHAPE = -2,        /* tensor shape violates the constraints above */
+  TOK_ENOMEM = -3,        /* device allocation failed (tok_model_create only) */
+  TOK_EDEVICE = -4,       /* a HIP runtime call or kernel launch failed */
+  TOK_EBUDGET = -5,       /* request can never fit the caller's memory budget */
+  TOK_EUNSUPPORTED = -6,  /* precision / mode not available in this build */
+  TOK_EWORKSPACE = -7     /* workspace smaller than tok_workspace_size */
+} tok_status;
+
+typedef enum {
+  TOK_F32 = 0,       /* fp32 operands, fp32 MFMA, fp32 activations */
+  TOK_BF16 = 1,      /* bf16 operands and activations, fp32 accumulate */
+  TOK_FP8_E4M3 = 2   /* fp8 e4m3 operands, per-output-channel fp32 scales */
+} tok_precision;
+
+typedef enum {
+  TOK_DROP_NONE = 0,       /* keep every token */
+  TOK_DROP_BERNOULLI = 1,  /* token i = (t*H2 + h)*W2 + w of clip c dropped when
+                              splitmix64(seed ^ c*0x9E3779B97F4A7C15 ^ i) >> 40
+                              < floor(rate * 2^24) */
+  TOK_DROP_ROWS = 2,       /* one draw per token-matrix row r = t*H2 + h with key
+                              0x5A5A5A5A00000000 | r; a dropped row is a lost
+                              packet of Sec. 6.2 and zeroes all W2 tokens */
+  TOK_DROP_EXTERNAL = 3    /* keep mask supplied by the caller (device, uint8) */
+} tok_drop_mode;
+
+/* Token-drop request.  clip_id0: the hash id of clip 0 of the batch; clip n
+ * uses clip_id0 + n, so a clip's mask does not depend on its batch-mates.
+ * protect_iframe != 0 never drops latent frame 0 (the GoP's I frame). */
+typedef struct {
+  int mode;                  /* tok_drop_mode */
+  float rate;                /* drop probability in [0, 1] (clamped) */
+  uint64_t seed;
+  uint64_t clip_id0;
+  int protect_iframe;
+  const uint8_t* ext_keep;   /* device (N,T2,H2,W2) for TOK_DROP_EXTERNAL, else NULL */
+} tok_drop_desc;
+
+typedef struct tok_model tok_model;
+
+/* What a workspace is sized for. */
+enum { TOK_WS_ENCODE = 1, TOK_WS_DECODE = 2, TOK_WS_ROUNDTRIP = 3 };
+
+/* Number of float32 values in the canonical weight blob (2,225,929): every
+ * tensor in module order (encoder conv_in, rb1, rb2, down1, down2, proj;
+ * decoder proj_in, up2, up1, rb1, rb2, conv_out), conv weights as
+ * [Cout][Cin][kt][kh][kw] followed by the bias [Cout]; each residual block is
+ * gn_a.gamma, gn_a.beta, a.w, a.b, gn_b.gamma, gn_b.beta, b.w, b.b. */
+size_t tok_weight_count(void);
+
+/* Copy the host float32 weight blob to `device`, convert it to `prec` and
+ * pack it into the kernels' layouts.  *out receives the model handle.  The
+ * model is read-only afterwards and may be used from several streams. */
+tok_status tok_model_create(const float* host_weights, size_t n_floats, tok_precision prec,
+                            int device, tok_model** out);
+void tok_model_destroy(tok_model* model);
+
+/* Bytes of device workspace that tok_encode / tok_decode need for a batch of
+ * N clips of T x H x W pixels (`what` = TOK_WS_ENCODE / DECODE / ROUNDTRIP). */
+tok_status tok_workspace_size(const tok_model* model, int N, int T, int H, int W, int what,
+                              size_t* bytes);
+
+/* Encoder f_phi followed by FSQ and the token mask, fused.
+ * x: uint8 (N,T,H,W,3).  z: float32 pre-quantisation latent or NULL.
+ * codes: float32 normalised codes, already multiplied by keep.  idx: int32
+ * code indices (a dropped token keeps its true index).  drop: NULL = keep all.
+ * keep: uint8 mask output or NULL.  ws: workspace of ws_bytes. */
+tok_status tok_encode(tok_model* model, const uint8_t* x, int N, int T, int H, int W, float* z,
+                      float* codes, int32_t* idx, const tok_drop_desc* drop, uint8_t* keep,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* FSQ alone on n_tokens float32 latent vectors z (n_tokens, 6):
+ * codes (n_tokens, 6) float32, idx (n_tokens) int32.  Either output may be NULL. */
+tok_status tok_quantize(const float* z, size_t n_tokens, float* codes, int32_t* idx,
+                        hipStream_t stream);
+
+/* Token dropping alone (Sec. 6.2 zero fill): builds keep (N,T2,H2,W2) from
+ * `drop` and multiplies codes (N,T2,H2,W2,6) by it in place.  codes or keep
+ * may be NULL (mask only / zero-fill only is not allowed: keep NULL means the
+ * mask is not stored). */
+tok_status tok_drop(const tok_drop_desc* drop, float* codes, uint8_t* keep, int N, int T2,
+                    int H2, int W2, hipStream_t stream);
+
+/* Decoder g_theta: codes float32 (N,T2,H2,W2,6) -> x_hat float32
+ * (N, 4(T2-1)+1, 4 H2, 4 W2, 3). */
+tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H2, int W2,
+                      float* xhat, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Per-kernel timing.  Between tok_profile_begin and tok_profile_end every
+ * kernel that tok_encode / tok_decode launch for `model` is bracketed by a
+ * pair of HIP events recorded on the caller's stream.  tok_profile_end waits
+ * for the last event, then writes for each kernel id k < n_ids the summed
+ * duration ms[k] and the launch count count[k] (either may be NULL) and
+ * frees the events.  Kernel ids: 0..15 the convolution layers in blob order
+ * (conv_in, enc rb1.a, rb1.b, rb2.a, rb2.b, down1, down2, proj, proj_in, up2,
+ * up1, dec rb1.a, rb1.b, rb2.a, rb2.b, conv_out; 7 and 8 are the fused
+ * projection kernels), 16 GroupNorm finalize; tok_kernel_name(k) names them.
+ * Profiling allocates events and is meant for measurement runs; do not
+ * profile one model from several host threads at once. */
+tok_status tok_profile_begin(tok_model* model);
+tok_status tok_profile_end(tok_model* model, int n_ids, double* ms, int* count);
+const char* tok_kernel_name(int k);
+
+const char* tok_status_str(tok_status s);
+const char* tok_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOK_H */

@@ -1,0 +1,75 @@
+"""ctypes loader for libtok.so: argument types of every entry point of
+include/tok.h.  Importing this module fails loudly if the library has not
+been built; there is no fallback implementation."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtok.so")
+
+TOK_OK = 0
+TOK_F32, TOK_BF16, TOK_FP8_E4M3 = 0, 1, 2
+TOK_DROP_NONE, TOK_DROP_BERNOULLI, TOK_DROP_ROWS, TOK_DROP_EXTERNAL = 0, 1, 2, 3
+TOK_WS_ENCODE, TOK_WS_DECODE, TOK_WS_ROUNDTRIP = 1, 2, 3
+
+
+class DropDesc(C.Structure):
+    """Mirror of tok_drop_desc."""
+    _fields_ = [("mode", C.c_int), ("rate", C.c_float), ("seed", C.c_uint64), ("clip_id0", C.c_uint64),
+                ("protect_iframe", C.c_int), ("ext_keep", C.c_void_p)]
+
+
+class TokError(RuntimeError):
+    def __init__(self, fn, status, detail):
+        super().__init__("%s failed: status %d (%s)" % (fn, status, detail))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtok.so is not built (%s); run python -m paper_2602_03529_amd.build" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp, sz, i32, f32p = C.c_void_p, C.c_size_t, C.c_int, C.c_void_p
+    L.tok_weight_count.restype = sz
+    L.tok_weight_count.argtypes = []
+    L.tok_model_create.restype = i32
+    L.tok_model_create.argtypes = [vp, sz, i32, i32, C.POINTER(vp)]
+    L.tok_model_destroy.restype = None
+    L.tok_model_destroy.argtypes = [vp]
+    L.tok_workspace_size.restype = i32
+    L.tok_workspace_size.argtypes = [vp, i32, i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_encode.restype = i32
+    L.tok_encode.argtypes = [vp, vp, i32, i32, i32, i32, f32p, f32p, vp, C.POINTER(DropDesc), vp, vp, sz, vp]
+    L.tok_quantize.restype = i32
+    L.tok_quantize.argtypes = [vp, sz, vp, vp, vp]
+    L.tok_drop.restype = i32
+    L.tok_drop.argtypes = [C.POINTER(DropDesc), vp, vp, i32, i32, i32, i32, vp]
+    L.tok_decode.restype = i32
+    L.tok_decode.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.tok_profile_begin.restype = i32
+    L.tok_profile_begin.argtypes = [vp]
+    L.tok_profile_end.restype = i32
+    L.tok_profile_end.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.tok_kernel_name.restype = C.c_char_p
+    L.tok_kernel_name.argtypes = [i32]
+    L.tok_status_str.restype = C.c_char_p
+    L.tok_status_str.argtypes = [i32]
+    L.tok_last_error.restype = C.c_char_p
+    L.tok_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def check(fn, status):
+    if status != TOK_OK:
+        L = lib()
+        detail = L.tok_status_str(status).decode() + ": " + L.tok_last_error().decode()
+        raise TokError(fn, status, detail)

@@ -1,0 +1,284 @@
+// Memory-bound kernels of the tokenizer path: GroupNorm statistics merge,
+// the 1x1x1 latent projections, finite scalar quantisation and token
+// dropping with zero fill (Sec. 6.2: dropped and lost tokens are both zeros).
+#include "tok_internal.h"
+#include "tok_device.h"
+
+namespace tok {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// GroupNorm finalize.  One block per frame (n, t); 32 groups x 8 lanes.
+// Lane j of group g merges tiles j, j+8, ... with Chan's pairwise update,
+// then the 8 lane results are merged in a fixed butterfly order, so the
+// result is deterministic and independent of the launch order of the
+// producing conv's workgroups.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void chan_merge(float& n, float& m, float& q, float nb, float mb, float qb) {
+  if (nb == 0.f) return;
+  if (n == 0.f) { n = nb; m = mb; q = qb; return; }
+  const float tot = n + nb;
+  const float d = mb - m;
+  const float f = nb / tot;
+  m = m + d * f;
+  q = q + qb + d * d * n * f;
+  n = tot;
+}
+
+__global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restrict__ stats, int tiles,
+                                                           const float* __restrict__ gamma,
+                                                           const float* __restrict__ beta, float eps,
+                                                           float* __restrict__ scale,
+                                                           float* __restrict__ shift) {
+  const int frame = blockIdx.x;
+  const int g = threadIdx.x >> 3, j = threadIdx.x & 7;
+  const float4* s = stats + (size_t)frame * tiles * 32;
+  float n = 0.f, m = 0.f, q = 0.f;
+  for (int t = j; t < tiles; t += 8) {
+    const float4 p = s[(size_t)t * 32 + g];
+    chan_merge(n, m, q, p.x, p.y, p.z);
+  }
+#pragma unroll
+  for (int off = 4; off >= 1; off >>= 1) {
+    const float nb = __shfl_xor(n, off), mb = __shfl_xor(m, off), qb = __shfl_xor(q, off);
+    // lower lane keeps itself as the left operand: same order on every lane pair
+    if ((j & off) == 0) chan_merge(n, m, q, nb, mb, qb);
+    else {
+      float n2 = nb, m2 = mb, q2 = qb;
+      chan_merge(n2, m2, q2, n, m, q);
+      n = n2; m = m2; q = q2;
+    }
+  }
+  if (j < 2) {
+    const int c = 2 * g + j;
+    const float var = q / n;
+    const float rstd = 1.0f / sqrtf(var + eps);
+    const float sc = rstd * gamma[c];
+    scale[(size_t)frame * 64 + c] = sc;
+    shift[(size_t)frame * 64 + c] = beta[c] - m * sc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FSQ (Mentzer et al.): b = tanh(z + s) h - o; q = rint(b) (half to even);
+// codes = q / floor(L/2); idx = sum (q + floor(L/2)) * basis.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fsq6(const float z[6], const FsqConst& fc, float codes[6], int* idx) {
+  int id = 0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const float b = tanhf(z[c] + fc.s[c]) * fc.h[c] - fc.o[c];
+    const float q = rintf(b);
+    codes[c] = q * fc.inv_d[c];
+    id += ((int)q + (int)fc.d[c]) * fc.basis[c];
+  }
+  *idx = id;
+}
+
+__device__ __forceinline__ uint8_t keep_bit(const DropArgs& d, int n, int t, int h, int w, int T2, int H2,
+                                            int W2) {
+  if (d.mode == 0) return 1;
+  if (d.protect_iframe && t == 0) return 1;
+  const size_t tok = (((size_t)n * T2 + t) * H2 + h) * W2 + w;
+  if (d.mode == 3) return d.ext_keep[tok] != 0;
+  const uint64_t base = d.seed ^ ((d.clip_id0 + (uint64_t)n) * 0x9E3779B97F4A7C15ull);
+  uint64_t key;
+  if (d.mode == 1) key = ((uint64_t)t * H2 + h) * W2 + w;
+  else key = 0x5A5A5A5A00000000ull | ((uint64_t)t * H2 + h);
+  const uint32_t u = (uint32_t)(splitmix64(base ^ key) >> 40);
+  return u >= d.thr ? 1 : 0;
+}
+
+// Level-2 activations (chunked, 128 ch) -> z (6) -> FSQ -> mask.  One thread
+// per token; the 6 x 128 projection lives in LDS.
+template <int PREC>
+__global__ void __launch_bounds__(256) proj_fsq_kernel(const void* __restrict__ act, int N, int T2, int H2,
+                                                        int W2, int in_chunks, const float* __restrict__ wp,
+                                                        const float* __restrict__ bp, FsqConst fc, DropArgs d,
+                                                        float* __restrict__ z, float* __restrict__ codes,
+                                                        int32_t* __restrict__ idx, uint8_t* __restrict__ keep) {
+  constexpr int CH = PREC == P_BF16 ? 32 : 16;
+  __shared__ float w[6 * 128];
+  for (int e = threadIdx.x; e < 6 * 128; e += blockDim.x) w[e] = wp[e];
+  __syncthreads();
+  const size_t HW = (size_t)H2 * W2;
+  const size_t ntok = (size_t)N * T2 * HW;
+  const size_t tok = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tok >= ntok) return;
+  const size_t frame = tok / HW, hw = tok % HW;
+  float acc[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) acc[c] = bp[c];
+  for (int ck = 0; ck < in_chunks; ++ck) {
+    const char* base = reinterpret_cast<const char*>(act) + ((frame * in_chunks + ck) * HW + hw) * kChunkBytes;
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      const uint4 v = reinterpret_cast<const uint4*>(base)[qd];
+      float x[8];
+      int ne;
+      if constexpr (PREC == P_BF16) {
+        x[0] = bf16_lo(v.x); x[1] = bf16_hi(v.x); x[2] = bf16_lo(v.y); x[3] = bf16_hi(v.y);
+        x[4] = bf16_lo(v.z); x[5] = bf16_hi(v.z); x[6] = bf16_lo(v.w); x[7] = bf16_hi(v.w);
+        ne = 8;
+      } else {
+        x[0] = __uint_as_float(v.x); x[1] = __uint_as_float(v.y);
+        x[2] = __uint_as_float(v.z); x[3] = __uint_as_float(v.w);
+        ne = 4;
+      }
+      const int c0 = ck * CH + qd * ne;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (e < ne) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) acc[c] = fmaf(w[c * 128 + c0 + e], x[e], acc[c]);
+        }
+      }
+    }
+  }
+  float cd[6];
+  int id;
+  fsq6(acc, fc, cd, &id);
+  const int n = (int)(frame / T2), t = (int)(frame % T2);
+  const int h = (int)(hw / W2), ww = (int)(hw % W2);
+  const uint8_t k = keep_bit(d, n, t, h, ww, T2, H2, W2);
+  if (z) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[tok * 6 + c] = acc[c];
+  }
+  if (codes) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) codes[tok * 6 + c] = k ? cd[c] : 0.f;
+  }
+  if (idx) idx[tok] = id;
+  if (keep) keep[tok] = k;
+}
+
+__global__ void __launch_bounds__(256) quantize_kernel(const float* __restrict__ z, size_t n, FsqConst fc,
+                                                        float* __restrict__ codes, int32_t* __restrict__ idx) {
+  const size_t tok = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tok >= n) return;
+  float zz[6], cd[6];
+  int id;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) zz[c] = z[tok * 6 + c];
+  fsq6(zz, fc, cd, &id);
+  if (codes) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) codes[tok * 6 + c] = cd[c];
+  }
+  if (idx) idx[tok] = id;
+}
+
+__global__ void __launch_bounds__(256) drop_kernel(DropArgs d, float* __restrict__ codes,
+                                                    uint8_t* __restrict__ keep, int N, int T2, int H2, int W2) {
+  const size_t ntok = (size_t)N * T2 * H2 * W2;
+  const size_t tok = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tok >= ntok) return;
+  const int ww = (int)(tok % W2);
+  size_t r = tok / W2;
+  const int h = (int)(r % H2);
+  r /= H2;
+  const int t = (int)(r % T2);
+  const int n = (int)(r / T2);
+  const uint8_t k = keep_bit(d, n, t, h, ww, T2, H2, W2);
+  if (keep) keep[tok] = k;
+  if (codes && !k) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) codes[tok * 6 + c] = 0.f;
+  }
+}
+
+// codes (6) -> 128 channels; one thread per (token, chunk) writes 64 bytes.
+template <int PREC>
+__global__ void __launch_bounds__(256) proj_in_kernel(const float* __restrict__ codes, size_t ntok,
+                                                       const float* __restrict__ wpin, const float* __restrict__ bpin,
+                                                       void* __restrict__ out, int out_chunks, int HW) {
+  constexpr int CH = PREC == P_BF16 ? 32 : 16;
+  __shared__ float w[128 * 6];
+  __shared__ float bsh[128];
+  for (int e = threadIdx.x; e < 128 * 6; e += blockDim.x) w[e] = wpin[e];
+  for (int e = threadIdx.x; e < 128; e += blockDim.x) bsh[e] = bpin[e];
+  __syncthreads();
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ntok * out_chunks) return;
+  const size_t tok = gid / out_chunks;
+  const int ck = (int)(gid % out_chunks);
+  const size_t frame = tok / HW, hw = tok % HW;
+  float c6[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) c6[c] = codes[tok * 6 + c];
+  float y[CH];
+#pragma unroll
+  for (int e = 0; e < CH; ++e) {
+    const int o = ck * CH + e;
+    float a = bsh[o];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a = fmaf(w[o * 6 + c], c6[c], a);
+    y[e] = a;
+  }
+  uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<char*>(out) +
+                                        ((frame * out_chunks + ck) * HW + hw) * kChunkBytes);
+#pragma unroll
+  for (int qd = 0; qd < 4; ++qd) {
+    if constexpr (PREC == P_BF16) {
+      dst[qd] = make_uint4(pack_bf16(y[qd * 8 + 0], y[qd * 8 + 1]), pack_bf16(y[qd * 8 + 2], y[qd * 8 + 3]),
+                           pack_bf16(y[qd * 8 + 4], y[qd * 8 + 5]), pack_bf16(y[qd * 8 + 6], y[qd * 8 + 7]));
+    } else {
+      dst[qd] = make_uint4(__float_as_uint(y[qd * 4 + 0]), __float_as_uint(y[qd * 4 + 1]),
+                           __float_as_uint(y[qd * 4 + 2]), __float_as_uint(y[qd * 4 + 3]));
+    }
+  }
+}
+
+inline unsigned blocks_for(size_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const float* gamma, const float* beta,
+                              float eps, float* scale, float* shift, hipStream_t s) {
+  hipLaunchKernelGGL(gn_finalize_kernel, dim3(frames), dim3(256), 0, s, stats, tiles, gamma, beta, eps, scale,
+                     shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_proj_fsq(const void* act, int prec, int N, int T2, int H2, int W2, int in_chunks,
+                           const float* wp, const float* bp, const FsqConst& fc, const DropArgs& d, float* z,
+                           float* codes, int32_t* idx, uint8_t* keep, hipStream_t s) {
+  const size_t ntok = (size_t)N * T2 * H2 * W2;
+  if (prec == P_BF16)
+    hipLaunchKernelGGL(proj_fsq_kernel<P_BF16>, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, act, N, T2, H2, W2,
+                       in_chunks, wp, bp, fc, d, z, codes, idx, keep);
+  else
+    hipLaunchKernelGGL(proj_fsq_kernel<P_F32>, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, act, N, T2, H2, W2,
+                       in_chunks, wp, bp, fc, d, z, codes, idx, keep);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* z, size_t n, const FsqConst& fc, float* codes, int32_t* idx,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(quantize_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, z, n, fc, codes, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_drop(const DropArgs& d, float* codes, uint8_t* keep, int N, int T2, int H2, int W2,
+                       hipStream_t s) {
+  const size_t ntok = (size_t)N * T2 * H2 * W2;
+  hipLaunchKernelGGL(drop_kernel, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, d, codes, keep, N, T2, H2, W2);
+  return hipGetLastError();
+}
+
+hipError_t launch_proj_in(const float* codes, size_t ntok, const float* w, const float* b, int prec, void* out,
+                          int out_chunks, int HW, hipStream_t s) {
+  const size_t n = ntok * out_chunks;
+  if (prec == P_BF16)
+    hipLaunchKernelGGL(proj_in_kernel<P_BF16>, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, ntok, w, b, out,
+                       out_chunks, HW);
+  else
+    hipLaunchKernelGGL(proj_in_kernel<P_F32>, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, ntok, w, b, out,
+                       out_chunks, HW);
+  return hipGetLastError();
+}
+
+}  // namespace tok

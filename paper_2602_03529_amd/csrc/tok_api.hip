@@ -1,0 +1,518 @@
+// C ABI of libtok.so: model packing, workspace planning and the launch
+// sequences of encode / decode (see include/tok.h for the contract).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tok.h"
+#include "tok_internal.h"
+
+using namespace tok;
+
+namespace {
+
+thread_local std::string g_err;
+
+tok_status fail(tok_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define TOK_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(TOK_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Parameter table (canonical blob order, see tok_weight_count in tok.h)
+// ---------------------------------------------------------------------------
+enum LayerId {
+  L_CONV_IN = 0, L_E_RB1_A, L_E_RB1_B, L_E_RB2_A, L_E_RB2_B, L_DOWN1, L_DOWN2, L_PROJ,
+  L_PROJ_IN, L_UP2, L_UP1, L_D_RB1_A, L_D_RB1_B, L_D_RB2_A, L_D_RB2_B, L_CONV_OUT, L_COUNT
+};
+enum NormId { N_E_RB1_A = 0, N_E_RB1_B, N_E_RB2_A, N_E_RB2_B, N_D_RB1_A, N_D_RB1_B, N_D_RB2_A, N_D_RB2_B, N_COUNT };
+
+struct ConvSpec { int cout, cin, k; };
+const ConvSpec kConv[L_COUNT] = {
+    {64, 3, 3},   {64, 64, 3},  {64, 64, 3},  {64, 64, 3},  {64, 64, 3},  {128, 64, 3},
+    {128, 128, 3}, {6, 128, 1}, {128, 6, 1},  {128, 128, 3}, {64, 128, 3}, {64, 64, 3},
+    {64, 64, 3},  {64, 64, 3},  {64, 64, 3},  {3, 64, 3}};
+
+struct BlobItem { int is_conv; int id; };  // conv layer or norm
+// module order: conv_in, rb1(gn_a, a, gn_b, b), rb2, down1, down2, proj, proj_in, up2, up1, rb1, rb2, conv_out
+const BlobItem kOrder[] = {
+    {1, L_CONV_IN},
+    {0, N_E_RB1_A}, {1, L_E_RB1_A}, {0, N_E_RB1_B}, {1, L_E_RB1_B},
+    {0, N_E_RB2_A}, {1, L_E_RB2_A}, {0, N_E_RB2_B}, {1, L_E_RB2_B},
+    {1, L_DOWN1}, {1, L_DOWN2}, {1, L_PROJ}, {1, L_PROJ_IN}, {1, L_UP2}, {1, L_UP1},
+    {0, N_D_RB1_A}, {1, L_D_RB1_A}, {0, N_D_RB1_B}, {1, L_D_RB1_B},
+    {0, N_D_RB2_A}, {1, L_D_RB2_A}, {0, N_D_RB2_B}, {1, L_D_RB2_B},
+    {1, L_CONV_OUT}};
+
+size_t blob_count() {
+  size_t n = 0;
+  for (const auto& it : kOrder) {
+    if (it.is_conv) {
+      const ConvSpec& c = kConv[it.id];
+      n += (size_t)c.cout * c.cin * c.k * c.k * c.k + c.cout;
+    } else {
+      n += 2 * 64;
+    }
+  }
+  return n;
+}
+
+constexpr float kGnEps = 1e-6f;
+const int kLevels[6] = {8, 8, 8, 5, 5, 5};
+
+FsqConst make_fsq_const() {
+  FsqConst f;
+  int basis = 1;
+  for (int c = 0; c < 6; ++c) {
+    const double L = kLevels[c];
+    const double h = (L - 1.0) * (1.0 - 1e-3) / 2.0;
+    const double o = (kLevels[c] % 2 == 0) ? 0.5 : 0.0;
+    const double d = std::floor(L / 2.0);
+    f.h[c] = (float)h;
+    f.o[c] = (float)o;
+    f.s[c] = (float)std::atanh(o / h);
+    f.d[c] = (float)d;
+    f.inv_d[c] = (float)(1.0 / d);
+    f.basis[c] = basis;
+    basis *= kLevels[c];
+  }
+  return f;
+}
+
+}  // namespace
+
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+};
+
+struct tok_model {
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  int device = 0;
+  int prec = P_BF16;
+  void* mem = nullptr;          // one device allocation holding everything below
+  const void* wpk[L_COUNT] = {};  // packed k=3 weights
+  int nt[L_COUNT] = {};
+  const float* bias[L_COUNT] = {};
+  const float* w1x1[L_COUNT] = {};  // plain fp32 [Cout][Cin] for the 1x1x1 layers
+  const float* gamma[N_COUNT] = {};
+  const float* beta[N_COUNT] = {};
+};
+
+namespace {
+
+struct Dims {
+  int N, T, H, W, T1, H1, W1, T2, H2, W2;
+};
+
+bool make_dims(int N, int T, int H, int W, Dims* d) {
+  if (N < 1 || T < 1 || H < 4 || W < 4) return false;
+  if ((T - 1) % 4 != 0 || H % 4 != 0 || W % 4 != 0) return false;
+  d->N = N; d->T = T; d->H = H; d->W = W;
+  d->T1 = (T - 1) / 2 + 1; d->H1 = H / 2; d->W1 = W / 2;
+  d->T2 = (d->T1 - 1) / 2 + 1; d->H2 = H / 4; d->W2 = W / 4;
+  return true;
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+  size_t l0, l1, l2, stats, scsh;
+  size_t off_l0a, off_l0b, off_l1, off_l2, off_stats, off_sc, off_sh, total;
+};
+
+Plan make_plan(const Dims& d, int prec) {
+  const size_t es = prec == P_BF16 ? 2 : 4;
+  Plan p;
+  p.l0 = align256((size_t)d.N * d.T * d.H * d.W * 64 * es);
+  p.l1 = align256((size_t)d.N * d.T1 * d.H1 * d.W1 * 128 * es);
+  p.l2 = align256((size_t)d.N * d.T2 * d.H2 * d.W2 * 128 * es);
+  const size_t tiles0 = (size_t)cdiv(d.H, 8) * cdiv(d.W, 64);
+  p.stats = align256((size_t)d.N * d.T * tiles0 * 32 * sizeof(float4));
+  p.scsh = align256((size_t)d.N * d.T * 64 * sizeof(float));
+  size_t o = 0;
+  p.off_l0a = o; o += p.l0;
+  p.off_l0b = o; o += p.l0;
+  p.off_l1 = o; o += p.l1;
+  p.off_l2 = o; o += p.l2;
+  p.off_stats = o; o += p.stats;
+  p.off_sc = o; o += p.scsh;
+  p.off_sh = o; o += p.scsh;
+  p.total = o;
+  return p;
+}
+
+struct Ws {
+  char* base;
+  Plan p;
+  void* l0a() const { return base + p.off_l0a; }
+  void* l0b() const { return base + p.off_l0b; }
+  void* l1() const { return base + p.off_l1; }
+  void* l2() const { return base + p.off_l2; }
+  float4* stats() const { return reinterpret_cast<float4*>(base + p.off_stats); }
+  float* sc() const { return reinterpret_cast<float*>(base + p.off_sc); }
+  float* sh() const { return reinterpret_cast<float*>(base + p.off_sh); }
+};
+
+constexpr int K_GN_FINAL = 16;
+constexpr int K_IDS = 17;
+const char* kKernelNames[K_IDS] = {
+    "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
+    "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
+    "dec.rb2.b", "dec.conv_out", "gn_finalize"};
+
+// Records an event pair around the launches made while it is alive (profiling only).
+struct Timed {
+  tok_model* m;
+  hipStream_t s;
+  ProfRec r;
+  bool on;
+  Timed(const tok_model* mc, int id, hipStream_t st) : m(const_cast<tok_model*>(mc)), s(st), on(mc->profiling) {
+    if (!on) return;
+    r.id = id;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) { on = false; return; }
+    hipEventRecord(r.a, s);
+  }
+  ~Timed() {
+    if (!on) return;
+    hipEventRecord(r.b, s);
+    m->prof.push_back(r);
+  }
+};
+
+// Generic conv launch helper.
+tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_kind, int N, int Ti, int Hi,
+                int Wi, int Cin, void* out, int out_kind, int To, int Ho, int Wo, const float* sc,
+                const float* sh, const void* resid, float4* stats, hipStream_t s) {
+  ConvLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  const int CH = m->prec == P_BF16 ? 32 : 16;
+  a.in = in;
+  a.N = N; a.Ti = Ti; a.Hi = Hi; a.Wi = Wi;
+  a.in_chunks = cdiv(Cin, CH);
+  a.Cin = Cin;
+  a.gn_scale = sc; a.gn_shift = sh;
+  a.wpk = m->wpk[layer];
+  a.bias = m->bias[layer];
+  a.Cout = kConv[layer].cout;
+  a.nt = m->nt[layer];
+  a.cout_tiles = cdiv(a.Cout, a.nt);
+  a.out = out;
+  a.resid = resid;
+  a.To = To; a.Ho = Ho; a.Wo = Wo;
+  a.out_chunks = cdiv(a.Cout, CH);
+  a.stats = stats;
+  int th, tw;
+  conv_tile(mode, &th, &tw);
+  a.tiles_h = cdiv(Ho, th);
+  a.tiles_w = cdiv(Wo, tw);
+  a.mode = mode; a.in_kind = in_kind; a.out_kind = out_kind; a.prec = m->prec;
+  Timed tm(m, layer, s);
+  const hipError_t e = launch_conv(a, s);
+  if (e != hipSuccess) return fail(TOK_EDEVICE, std::string("conv layer ") + std::to_string(layer) + ": " + hipGetErrorString(e));
+  return TOK_OK;
+}
+
+tok_status gn_final(const tok_model* m, int norm, const Ws& w, int frames, int Ho, int Wo, hipStream_t s) {
+  const int tiles = cdiv(Ho, 8) * cdiv(Wo, 64);
+  Timed tm(m, K_GN_FINAL, s);
+  const hipError_t e = launch_gn_finalize(w.stats(), frames, tiles, m->gamma[norm], m->beta[norm], kGnEps, w.sc(), w.sh(), s);
+  if (e != hipSuccess) return fail(TOK_EDEVICE, std::string("gn_finalize: ") + hipGetErrorString(e));
+  return TOK_OK;
+}
+
+#define TOK_TRY(x)                 \
+  do {                             \
+    tok_status s_ = (x);           \
+    if (s_ != TOK_OK) return s_;   \
+  } while (0)
+
+// Two residual blocks at level 0, in place on buffer A (B is scratch).
+// Entry: A holds the block input and (sc, sh) hold GN_a of the first block.
+tok_status resblocks(const tok_model* m, int first_layer, int first_norm, const Ws& w, const Dims& d,
+                     bool last_stats, hipStream_t s) {
+  const int N = d.N, T = d.T, H = d.H, W = d.W;
+  for (int r = 0; r < 2; ++r) {
+    const int la = first_layer + 2 * r, lb = la + 1;
+    const int na = first_norm + 2 * r, nb = na + 1;
+    (void)na;
+    // unit a: B = conv_a(silu(gn_a(A)))   (+ stats for gn_b)
+    TOK_TRY(conv(m, la, CM_S1, w.l0a(), IN_ACT, N, T, H, W, 64, w.l0b(), OUT_ACT, T, H, W, w.sc(), w.sh(), nullptr,
+                 w.stats(), s));
+    TOK_TRY(gn_final(m, nb, w, N * T, H, W, s));
+    // unit b: A = A + conv_b(silu(gn_b(B)))   (+ stats for the next block's gn_a)
+    const bool stats = (r == 0) || last_stats;
+    TOK_TRY(conv(m, lb, CM_S1, w.l0b(), IN_ACT, N, T, H, W, 64, w.l0a(), OUT_ACT, T, H, W, w.sc(), w.sh(), w.l0a(),
+                 stats ? w.stats() : nullptr, s));
+    if (r == 0) TOK_TRY(gn_final(m, first_norm + 2, w, N * T, H, W, s));
+  }
+  return TOK_OK;
+}
+
+bool valid_drop(const tok_drop_desc* dd) {
+  return !dd || (dd->mode >= 0 && dd->mode <= 3 && (dd->mode != TOK_DROP_EXTERNAL || dd->ext_keep));
+}
+
+DropArgs make_drop(const tok_drop_desc* dd) {
+  DropArgs a;
+  std::memset(&a, 0, sizeof(a));
+  if (!dd) return a;
+  a.mode = dd->mode;
+  double r = dd->rate;
+  if (!(r >= 0.0)) r = 0.0;
+  if (r > 1.0) r = 1.0;
+  a.thr = (uint32_t)std::floor(r * 16777216.0);
+  a.seed = dd->seed;
+  a.clip_id0 = dd->clip_id0;
+  a.protect_iframe = dd->protect_iframe;
+  a.ext_keep = dd->ext_keep;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tok_weight_count(void) { return blob_count(); }
+
+const char* tok_status_str(tok_status s) {
+  switch (s) {
+    case TOK_OK: return "ok";
+    case TOK_EINVAL: return "invalid argument";
+    case TOK_ESHAPE: return "invalid shape";
+    case TOK_ENOMEM: return "out of device memory";
+    case TOK_EDEVICE: return "device error";
+    case TOK_EBUDGET: return "over memory budget";
+    case TOK_EUNSUPPORTED: return "unsupported";
+    case TOK_EWORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+const char* tok_last_error(void) { return g_err.c_str(); }
+
+const char* tok_kernel_name(int k) { return (k >= 0 && k < K_IDS) ? kKernelNames[k] : "unknown"; }
+
+tok_status tok_profile_begin(tok_model* m) {
+  if (!m) return fail(TOK_EINVAL, "null model");
+  m->profiling = true;
+  return TOK_OK;
+}
+
+tok_status tok_profile_end(tok_model* m, int n_ids, double* ms, int* count) {
+  if (!m) return fail(TOK_EINVAL, "null model");
+  m->profiling = false;
+  for (int k = 0; k < n_ids; ++k) {
+    if (ms) ms[k] = 0.0;
+    if (count) count[k] = 0;
+  }
+  tok_status st = TOK_OK;
+  for (auto& r : m->prof) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      st = fail(TOK_EDEVICE, "event timing failed");
+    } else if (r.id >= 0 && r.id < n_ids) {
+      if (ms) ms[r.id] += t;
+      if (count) count[r.id] += 1;
+    }
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  m->prof.clear();
+  return st;
+}
+
+tok_status tok_model_create(const float* host_weights, size_t n_floats, tok_precision prec, int device,
+                            tok_model** out) {
+  if (!host_weights || !out) return fail(TOK_EINVAL, "null argument");
+  if (n_floats != blob_count()) return fail(TOK_EINVAL, "weight blob has " + std::to_string(n_floats) +
+                                                           " floats, expected " + std::to_string(blob_count()));
+  if (prec != TOK_F32 && prec != TOK_BF16) return fail(TOK_EUNSUPPORTED, "precision not available");
+  const int P = prec == TOK_BF16 ? P_BF16 : P_F32;
+  const size_t es = P == P_BF16 ? 2 : 4;
+
+  // Host staging: compute the device layout and fill one host buffer.
+  std::vector<size_t> conv_off(L_COUNT), bias_off(L_COUNT), w1_off(L_COUNT), g_off(N_COUNT), b_off(N_COUNT);
+  std::vector<const float*> src_w(L_COUNT), src_b(L_COUNT), src_g(N_COUNT), src_be(N_COUNT);
+  const float* cur = host_weights;
+  for (const auto& it : kOrder) {
+    if (it.is_conv) {
+      const ConvSpec& c = kConv[it.id];
+      src_w[it.id] = cur;
+      cur += (size_t)c.cout * c.cin * c.k * c.k * c.k;
+      src_b[it.id] = cur;
+      cur += c.cout;
+    } else {
+      src_g[it.id] = cur; cur += 64;
+      src_be[it.id] = cur; cur += 64;
+    }
+  }
+  size_t off = 0;
+  int nt[L_COUNT] = {};
+  for (int l = 0; l < L_COUNT; ++l) {
+    const ConvSpec& c = kConv[l];
+    if (c.k == 3) {
+      conv_off[l] = off;
+      off = align256(off + packed_conv_elems(c.cout, c.cin, P, &nt[l]) * es);
+    } else {
+      w1_off[l] = off;
+      off = align256(off + (size_t)c.cout * c.cin * 4);
+    }
+    bias_off[l] = off;
+    off = align256(off + (size_t)c.cout * 4);
+  }
+  for (int n = 0; n < N_COUNT; ++n) {
+    g_off[n] = off; off = align256(off + 64 * 4);
+    b_off[n] = off; off = align256(off + 64 * 4);
+  }
+  std::vector<char> host(off, 0);
+  for (int l = 0; l < L_COUNT; ++l) {
+    const ConvSpec& c = kConv[l];
+    if (c.k == 3) pack_conv_weights(src_w[l], c.cout, c.cin, P, host.data() + conv_off[l]);
+    else std::memcpy(host.data() + w1_off[l], src_w[l], (size_t)c.cout * c.cin * 4);
+    std::memcpy(host.data() + bias_off[l], src_b[l], (size_t)c.cout * 4);
+  }
+  for (int n = 0; n < N_COUNT; ++n) {
+    std::memcpy(host.data() + g_off[n], src_g[n], 64 * 4);
+    std::memcpy(host.data() + b_off[n], src_be[n], 64 * 4);
+  }
+
+  int prev = 0;
+  TOK_HIP(hipGetDevice(&prev));
+  TOK_HIP(hipSetDevice(device));
+  void* mem = nullptr;
+  if (hipMalloc(&mem, off) != hipSuccess) {
+    hipSetDevice(prev);
+    return fail(TOK_ENOMEM, "hipMalloc of model weights failed");
+  }
+  hipError_t e = hipMemcpy(mem, host.data(), off, hipMemcpyHostToDevice);
+  hipSetDevice(prev);
+  if (e != hipSuccess) {
+    hipFree(mem);
+    return fail(TOK_EDEVICE, std::string("weight upload: ") + hipGetErrorString(e));
+  }
+  tok_model* m = new (std::nothrow) tok_model;
+  if (!m) {
+    hipFree(mem);
+    return fail(TOK_ENOMEM, "host allocation failed");
+  }
+  m->device = device;
+  m->prec = P;
+  m->mem = mem;
+  char* base = static_cast<char*>(mem);
+  for (int l = 0; l < L_COUNT; ++l) {
+    if (kConv[l].k == 3) m->wpk[l] = base + conv_off[l];
+    else m->w1x1[l] = reinterpret_cast<const float*>(base + w1_off[l]);
+    m->bias[l] = reinterpret_cast<const float*>(base + bias_off[l]);
+    m->nt[l] = nt[l];
+  }
+  for (int n = 0; n < N_COUNT; ++n) {
+    m->gamma[n] = reinterpret_cast<const float*>(base + g_off[n]);
+    m->beta[n] = reinterpret_cast<const float*>(base + b_off[n]);
+  }
+  *out = m;
+  return TOK_OK;
+}
+
+void tok_model_destroy(tok_model* m) {
+  if (!m) return;
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(m->device);
+  hipFree(m->mem);
+  hipSetDevice(prev);
+  delete m;
+}
+
+tok_status tok_workspace_size(const tok_model* m, int N, int T, int H, int W, int what, size_t* bytes) {
+  if (!m || !bytes) return fail(TOK_EINVAL, "null argument");
+  if (what < TOK_WS_ENCODE || what > TOK_WS_ROUNDTRIP) return fail(TOK_EINVAL, "bad workspace kind");
+  Dims d;
+  if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
+  *bytes = make_plan(d, m->prec).total;
+  return TOK_OK;
+}
+
+tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W, float* z, float* codes,
+                      int32_t* idx, const tok_drop_desc* drop, uint8_t* keep, void* ws, size_t ws_bytes,
+                      hipStream_t s) {
+  if (!m || !x || !ws) return fail(TOK_EINVAL, "null argument");
+  if (!valid_drop(drop)) return fail(TOK_EINVAL, "bad drop descriptor");
+  Dims d;
+  if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
+  const Plan p = make_plan(d, m->prec);
+  if (ws_bytes < p.total) return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
+  Ws w{static_cast<char*>(ws), p};
+  // conv_in: u8 -> level 0 (+ stats for enc.rb1.gn_a)
+  TOK_TRY(conv(m, L_CONV_IN, CM_S1, x, IN_U8, N, T, H, W, 3, w.l0a(), OUT_ACT, T, H, W, nullptr, nullptr, nullptr,
+               w.stats(), s));
+  TOK_TRY(gn_final(m, N_E_RB1_A, w, N * T, H, W, s));
+  TOK_TRY(resblocks(m, L_E_RB1_A, N_E_RB1_A, w, d, false, s));
+  TOK_TRY(conv(m, L_DOWN1, CM_S2, w.l0a(), IN_ACT, N, T, H, W, 64, w.l1(), OUT_ACT, d.T1, d.H1, d.W1, nullptr,
+               nullptr, nullptr, nullptr, s));
+  TOK_TRY(conv(m, L_DOWN2, CM_S2, w.l1(), IN_ACT, N, d.T1, d.H1, d.W1, 128, w.l2(), OUT_ACT, d.T2, d.H2, d.W2,
+               nullptr, nullptr, nullptr, nullptr, s));
+  const FsqConst fc = make_fsq_const();
+  const DropArgs da = make_drop(drop);
+  const int CH = m->prec == P_BF16 ? 32 : 16;
+  Timed tm(m, L_PROJ, s);
+  TOK_HIP(launch_proj_fsq(w.l2(), m->prec, N, d.T2, d.H2, d.W2, 128 / CH, m->w1x1[L_PROJ], m->bias[L_PROJ], fc, da,
+                          z, codes, idx, keep, s));
+  return TOK_OK;
+}
+
+tok_status tok_quantize(const float* z, size_t n_tokens, float* codes, int32_t* idx, hipStream_t s) {
+  if (n_tokens && !z) return fail(TOK_EINVAL, "null z");
+  const FsqConst fc = make_fsq_const();
+  TOK_HIP(launch_quantize(z, n_tokens, fc, codes, idx, s));
+  return TOK_OK;
+}
+
+tok_status tok_drop(const tok_drop_desc* drop, float* codes, uint8_t* keep, int N, int T2, int H2, int W2,
+                    hipStream_t s) {
+  if (!drop || !valid_drop(drop)) return fail(TOK_EINVAL, "bad drop descriptor");
+  if (N < 1 || T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
+  if (!codes && !keep) return TOK_OK;
+  TOK_HIP(launch_drop(make_drop(drop), codes, keep, N, T2, H2, W2, s));
+  return TOK_OK;
+}
+
+tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, int W2, float* xhat, void* ws,
+                      size_t ws_bytes, hipStream_t s) {
+  if (!m || !codes || !xhat || !ws) return fail(TOK_EINVAL, "null argument");
+  if (T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
+  Dims d;
+  if (!make_dims(N, 4 * (T2 - 1) + 1, 4 * H2, 4 * W2, &d)) return fail(TOK_ESHAPE, "bad latent shape");
+  const Plan p = make_plan(d, m->prec);
+  if (ws_bytes < p.total) return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
+  Ws w{static_cast<char*>(ws), p};
+  const int CH = m->prec == P_BF16 ? 32 : 16;
+  {
+    Timed tm(m, L_PROJ_IN, s);
+    TOK_HIP(launch_proj_in(codes, (size_t)N * T2 * H2 * W2, m->w1x1[L_PROJ_IN], m->bias[L_PROJ_IN], m->prec,
+                           w.l2(), 128 / CH, H2 * W2, s));
+  }
+  TOK_TRY(conv(m, L_UP2, CM_UP, w.l2(), IN_ACT, N, d.T2, d.H2, d.W2, 128, w.l1(), OUT_ACT, d.T1, d.H1, d.W1,
+               nullptr, nullptr, nullptr, nullptr, s));
+  TOK_TRY(conv(m, L_UP1, CM_UP, w.l1(), IN_ACT, N, d.T1, d.H1, d.W1, 128, w.l0a(), OUT_ACT, d.T, d.H, d.W,
+               nullptr, nullptr, nullptr, w.stats(), s));
+  TOK_TRY(gn_final(m, N_D_RB1_A, w, N * d.T, d.H, d.W, s));
+  TOK_TRY(resblocks(m, L_D_RB1_A, N_D_RB1_A, w, d, false, s));
+  TOK_TRY(conv(m, L_CONV_OUT, CM_S1, w.l0a(), IN_ACT, N, d.T, d.H, d.W, 64, xhat, OUT_RGB32, d.T, d.H, d.W, nullptr,
+               nullptr, nullptr, nullptr, s));
+  return TOK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+"""Thin PyTorch binding of libtok.so: the C-ABI entry points with torch
+tensors for device memory and torch's current HIP stream.  Argument
+marshalling only; every step of the tokenizer runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"f32": L.TOK_F32, "bf16": L.TOK_BF16, "fp8": L.TOK_FP8_E4M3}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s cuda tensor of shape %s, got %s %s" %
+                         (name, dtype, tuple(shape), t.dtype, tuple(t.shape)))
+
+
+def latent_shape(T, H, W):
+    return (T - 1) // 4 + 1, H // 4, W // 4
+
+
+@dataclass
+class Drop:
+    """Token-drop request (tok_drop_desc)."""
+    mode: int = L.TOK_DROP_NONE
+    rate: float = 0.0
+    seed: int = 0
+    clip_id0: int = 0
+    protect_iframe: bool = False
+    ext_keep: torch.Tensor | None = None
+
+    def desc(self):
+        return L.DropDesc(int(self.mode), float(self.rate), int(self.seed) & (2**64 - 1),
+                          int(self.clip_id0) & (2**64 - 1), int(bool(self.protect_iframe)),
+                          None if self.ext_keep is None else self.ext_keep.data_ptr())
+
+
+def weight_count() -> int:
+    return int(L.lib().tok_weight_count())
+
+
+class TokModel:
+    """A tok_model: weights packed on one device in one precision."""
+
+    def __init__(self, weights_flat: np.ndarray, precision: str = "bf16", device: int = 0):
+        w = np.ascontiguousarray(weights_flat, dtype=np.float32)
+        self.lib = L.lib()
+        self.device = device
+        self.precision = precision
+        h = C.c_void_p()
+        L.check("tok_model_create", self.lib.tok_model_create(
+            w.ctypes.data_as(C.c_void_p), w.size, PRECISIONS[precision], device, C.byref(h)))
+        self.handle = h
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            self.lib.tok_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self, N, T, H, W, what=L.TOK_WS_ROUNDTRIP) -> int:
+        n = C.c_size_t()
+        L.check("tok_workspace_size", self.lib.tok_workspace_size(self.handle, N, T, H, W, what, C.byref(n)))
+        return int(n.value)
+
+    def workspace(self, N, T, H, W, what=L.TOK_WS_ROUNDTRIP):
+        """A cached uint8 device tensor large enough for (N, T, H, W)."""
+        need = self.workspace_size(N, T, H, W, what)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda:%d" % self.device)
+        return self._ws
+
+    def encode(self, x: torch.Tensor, drop: Drop | None = None, z=True, keep=True, out=None, ws=None):
+        """x: uint8 (N,T,H,W,3) -> dict(z, codes, idx, keep)."""
+        N, T, H, W, _ = x.shape
+        _need(x, torch.uint8, (N, T, H, W, 3), "x")
+        T2, H2, W2 = latent_shape(T, H, W)
+        dev = x.device
+        o = out or {}
+        zt = o.get("z") if o.get("z") is not None else (torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=dev) if z else None)
+        codes = o.get("codes") if o.get("codes") is not None else torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=dev)
+        idx = o.get("idx") if o.get("idx") is not None else torch.empty((N, T2, H2, W2), dtype=torch.int32, device=dev)
+        kp = o.get("keep") if o.get("keep") is not None else (torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None)
+        if ws is None:
+            ws = self.workspace(N, T, H, W)
+        d = drop.desc() if drop is not None else None
+        L.check("tok_encode", self.lib.tok_encode(
+            self.handle, _ptr(x), N, T, H, W, _ptr(zt), _ptr(codes), _ptr(idx),
+            C.byref(d) if d is not None else None, _ptr(kp), _ptr(ws), ws.numel(), _stream(dev)))
+        return dict(z=zt, codes=codes, idx=idx, keep=kp)
+
+    def decode(self, codes: torch.Tensor, out=None, ws=None):
+        """codes: float32 (N,T2,H2,W2,6) -> x_hat float32 (N,4(T2-1)+1,4H2,4W2,3)."""
+        N, T2, H2, W2, _ = codes.shape
+        _need(codes, torch.float32, (N, T2, H2, W2, 6), "codes")
+        T, H, W = 4 * (T2 - 1) + 1, 4 * H2, 4 * W2
+        xh = out if out is not None else torch.empty((N, T, H, W, 3), dtype=torch.float32, device=codes.device)
+        if ws is None:
+            ws = self.workspace(N, T, H, W)
+        L.check("tok_decode", self.lib.tok_decode(self.handle, _ptr(codes), N, T2, H2, W2, _ptr(xh), _ptr(ws),
+                                                  ws.numel(), _stream(codes.device)))
+        return xh
+
+
+KERNEL_IDS = 17
+
+
+class Profile:
+    """Context manager: per-kernel HIP-event timing of the model's launches."""
+
+    def __init__(self, model: "TokModel"):
+        self.model = model
+        self.ms = {}
+        self.count = {}
+
+    def __enter__(self):
+        L.check("tok_profile_begin", self.model.lib.tok_profile_begin(self.model.handle))
+        return self
+
+    def __exit__(self, *exc):
+        ms = (C.c_double * KERNEL_IDS)()
+        cnt = (C.c_int * KERNEL_IDS)()
+        L.check("tok_profile_end", self.model.lib.tok_profile_end(self.model.handle, KERNEL_IDS, ms, cnt))
+        for k in range(KERNEL_IDS):
+            name = self.model.lib.tok_kernel_name(k).decode()
+            self.ms[name] = ms[k]
+            self.count[name] = cnt[k]
+        return False
+
+
+def quantize(z: torch.Tensor):
+    """FSQ of float32 (..., 6) latents -> (codes, idx)."""
+    assert z.dtype == torch.float32 and z.shape[-1] == 6 and z.is_cuda and z.is_contiguous()
+    n = z.numel() // 6
+    codes = torch.empty_like(z)
+    idx = torch.empty(z.shape[:-1], dtype=torch.int32, device=z.device)
+    L.check("tok_quantize", L.lib().tok_quantize(_ptr(z), n, _ptr(codes), _ptr(idx), _stream(z.device)))
+    return codes, idx
+
+
+def drop(codes: torch.Tensor | None, d: Drop, shape=None, keep=True):
+    """Zero-fill codes (N,T2,H2,W2,6) in place by the mask of `d`; returns keep."""
+    if codes is not None:
+        N, T2, H2, W2, _ = codes.shape
+        dev = codes.device
+    else:
+        N, T2, H2, W2 = shape
+        dev = torch.device("cuda")
+    kp = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None
+    desc = d.desc()
+    L.check("tok_drop", L.lib().tok_drop(C.byref(desc), _ptr(codes), _ptr(kp), N, T2, H2, W2, _stream(dev)))
+    return kp
