@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--cpu-crop", type=str, default="180x320", help="HxW crop of clip 0 frame 0 for the oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (clips shard across GPUs "
@@ -84,6 +86,15 @@ def main():
     print("bench: generating %dx%dx%dx%d synthetic clips" % (N, T, H, W), file=sys.stderr, flush=True)
     x = torch.from_numpy(synth.make_batch(list(range(N)), T, H, W)).to(dev)
     wflat = synth.flatten_weights(synth.make_weights(1))
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: calibration copy of %d bytes done" % nb, file=sys.stderr, flush=True)
+        del src, dst
     T2, H2, W2 = tok.latent_shape(T, H, W)
 
     def make_runner(prec):

@@ -95,8 +95,13 @@ typedef struct {
 
 typedef struct tok_model tok_model;
 
-/* What a workspace is sized for. */
-enum { TOK_WS_ENCODE = 1, TOK_WS_DECODE = 2, TOK_WS_ROUNDTRIP = 3 };
+/* What a workspace is sized for.  TOK_WS_STREAM (or-ed in) sizes it for
+ * causal temporal chunking: the clip is processed one latent frame (4 input
+ * frames) at a time, each layer keeping the last 1-2 frames of its input, so
+ * the workspace does not grow with T and the results are those of whole-clip
+ * processing.  tok_encode / tok_decode process the whole clip at once when
+ * the workspace they are given allows it, else in chunks. */
+enum { TOK_WS_ENCODE = 1, TOK_WS_DECODE = 2, TOK_WS_ROUNDTRIP = 3, TOK_WS_STREAM = 16 };
 
 /* Number of float32 values in the canonical weight blob (2,225,929): every
  * tensor in module order (encoder conv_in, rb1, rb2, down1, down2, proj;
@@ -157,6 +162,71 @@ tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H
 tok_status tok_profile_begin(tok_model* model);
 tok_status tok_profile_end(tok_model* model, int n_ids, double* ms, int* count);
 const char* tok_kernel_name(int k);
+
+/* ---------------------------------------------------------------------------
+ * Streaming request loop (continuous batching under an HBM budget).
+ *
+ * The paper streams every 9-frame GoP through the codec in real time
+ * (Sec. 7 codec wrapper: weights stay resident; Sec. 6: the sender encodes and
+ * the receiver decodes continuously).  A tok_server owns one device arena of
+ * `budget_bytes` (allocated once, at create) and `slots` HIP streams.  A
+ * scheduler thread admits queued clips, oldest first, whenever a stream slot
+ * is free and the clip's memory fits in the arena; queued clips of identical
+ * shape (up to `max_batch`) are admitted together as one batched launch.
+ * Admitted work runs asynchronously and overlaps with work on the other
+ * slots; memory returns to the arena when the client releases a result.
+ * A clip's result does not depend on what it was batched with.
+ * -------------------------------------------------------------------------*/
+typedef struct tok_server tok_server;
+
+typedef struct {
+  int T, H, W;              /* clip shape (T % 4 == 1, H and W multiples of 4) */
+  const uint8_t* pixels;    /* host (T,H,W,3) uint8; copied to the device at admission
+                               (pinned memory makes the copy asynchronous) */
+  tok_drop_desc drop;       /* per-clip token drop (NONE, BERNOULLI or ROWS); clip_id0 is
+                               this clip's hash id */
+} tok_request;
+
+typedef struct {
+  uint64_t ticket;
+  tok_status status;        /* TOK_OK, or the error that ended the request */
+  int T2, H2, W2;           /* latent grid */
+  const float* codes;       /* device (T2,H2,W2,6), zero-filled by the drop mask */
+  const int32_t* idx;       /* device (T2,H2,W2) */
+  const uint8_t* keep;      /* device (T2,H2,W2) */
+  const float* xhat;        /* device (T,H,W,3) reconstruction */
+  double queue_ms;          /* submit -> admission */
+  double run_ms;            /* admission -> completion observed by the scheduler */
+  double total_ms;          /* submit -> completion */
+  int batch_size;           /* clips in the launch this request ran in */
+} tok_result;
+
+/* Device bytes one clip of T x H x W occupies at least while admitted
+ * (streaming workspace, pixels, latents and reconstruction).  The server runs
+ * a launch on the whole-clip workspace when that takes at most a quarter of
+ * the arena, else in causal temporal chunks. */
+tok_status tok_server_request_bytes(const tok_model* model, int T, int H, int W, size_t* bytes);
+tok_status tok_server_create(tok_model* model, size_t budget_bytes, int slots, int max_batch,
+                             tok_server** out);
+/* Queue a request; returns at once.  TOK_EBUDGET if the clip can never fit
+ * the budget, TOK_ESHAPE for a bad shape (the request is not queued). */
+tok_status tok_server_submit(tok_server* server, const tok_request* req, uint64_t* ticket);
+/* Wait up to timeout_ms (negative: forever) for a request to finish.
+ * TOK_OK with *out filled when done; TOK_EINVAL for an unknown ticket;
+ * 1 (positive) when the time-out expired first. */
+int tok_server_wait(tok_server* server, uint64_t ticket, int timeout_ms, tok_result* out);
+/* Copy a finished request's results into caller buffers (device pointers,
+ * any may be NULL; shapes as in tok_result), asynchronously on `stream`. */
+tok_status tok_server_copy_result(tok_server* server, uint64_t ticket, float* codes, int32_t* idx,
+                                  uint8_t* keep, float* xhat, hipStream_t stream);
+/* Return a finished request's memory to the arena; its result pointers die. */
+tok_status tok_server_release(tok_server* server, uint64_t ticket);
+/* Counters: queued, running and finished requests, arena bytes in use and
+ * the high-water mark. */
+tok_status tok_server_stats(tok_server* server, int* queued, int* running, int* finished,
+                            size_t* bytes_in_use, size_t* bytes_peak);
+/* Waits for admitted work, fails queued requests, frees the arena. */
+void tok_server_destroy(tok_server* server);
 
 const char* tok_status_str(tok_status s);
 const char* tok_last_error(void);

@@ -12,13 +12,26 @@ LIB_PATH = os.path.join(HERE, "libtok.so")
 TOK_OK = 0
 TOK_F32, TOK_BF16, TOK_FP8_E4M3 = 0, 1, 2
 TOK_DROP_NONE, TOK_DROP_BERNOULLI, TOK_DROP_ROWS, TOK_DROP_EXTERNAL = 0, 1, 2, 3
-TOK_WS_ENCODE, TOK_WS_DECODE, TOK_WS_ROUNDTRIP = 1, 2, 3
+TOK_WS_ENCODE, TOK_WS_DECODE, TOK_WS_ROUNDTRIP, TOK_WS_STREAM = 1, 2, 3, 16
 
 
 class DropDesc(C.Structure):
     """Mirror of tok_drop_desc."""
     _fields_ = [("mode", C.c_int), ("rate", C.c_float), ("seed", C.c_uint64), ("clip_id0", C.c_uint64),
                 ("protect_iframe", C.c_int), ("ext_keep", C.c_void_p)]
+
+
+class Request(C.Structure):
+    """Mirror of tok_request."""
+    _fields_ = [("T", C.c_int), ("H", C.c_int), ("W", C.c_int), ("pixels", C.c_void_p), ("drop", DropDesc)]
+
+
+class Result(C.Structure):
+    """Mirror of tok_result."""
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int), ("T2", C.c_int), ("H2", C.c_int), ("W2", C.c_int),
+                ("codes", C.c_void_p), ("idx", C.c_void_p), ("keep", C.c_void_p), ("xhat", C.c_void_p),
+                ("queue_ms", C.c_double), ("run_ms", C.c_double), ("total_ms", C.c_double),
+                ("batch_size", C.c_int)]
 
 
 class TokError(RuntimeError):
@@ -60,6 +73,22 @@ def lib():
     L.tok_profile_end.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.tok_kernel_name.restype = C.c_char_p
     L.tok_kernel_name.argtypes = [i32]
+    L.tok_server_request_bytes.restype = i32
+    L.tok_server_request_bytes.argtypes = [vp, i32, i32, i32, C.POINTER(sz)]
+    L.tok_server_create.restype = i32
+    L.tok_server_create.argtypes = [vp, sz, i32, i32, C.POINTER(vp)]
+    L.tok_server_submit.restype = i32
+    L.tok_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+    L.tok_server_wait.restype = i32
+    L.tok_server_wait.argtypes = [vp, C.c_uint64, i32, C.POINTER(Result)]
+    L.tok_server_copy_result.restype = i32
+    L.tok_server_copy_result.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, vp]
+    L.tok_server_release.restype = i32
+    L.tok_server_release.argtypes = [vp, C.c_uint64]
+    L.tok_server_stats.restype = i32
+    L.tok_server_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(sz), C.POINTER(sz)]
+    L.tok_server_destroy.restype = None
+    L.tok_server_destroy.argtypes = [vp]
     L.tok_status_str.restype = C.c_char_p
     L.tok_status_str.argtypes = [i32]
     L.tok_last_error.restype = C.c_char_p

@@ -18,9 +18,9 @@
 // Workgroup = 4 waves.  A workgroup owns one output frame (n, t), a TH x TW
 // spatial tile and nt output channels.  The K loop runs over the 3 temporal
 // taps x the 64-byte input-channel chunks; per step it stages into LDS
-//   * the spatial halo of one input frame / chunk (with the GroupNorm+SiLU
-//     prologue applied while staging), and
+//   * the spatial halo of one input frame / chunk, and
 //   * the 9 spatial taps of packed weights for that (kt, chunk),
+// both with direct global->LDS loads (no VGPR staging),
 // then every wave runs 9 taps x (its position blocks x channel blocks) MFMAs.
 // 16-byte quads inside a 64-byte LDS row are XOR-swizzled by the row index so
 // that the 16 lanes reading 16 consecutive rows hit distinct banks.
@@ -34,22 +34,51 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 
-__device__ __forceinline__ int swz(int row) { return (row >> 1) & 3; }
+#ifndef TOK_SWZ_SHIFT
+#define TOK_SWZ_SHIFT 1
+#endif
+__host__ __device__ __forceinline__ int swz(int row) { return (row >> TOK_SWZ_SHIFT) & 3; }
 
 template <int PREC> struct Op;
 template <> struct Op<P_F32> { static constexpr int CH = 16; static constexpr int QE = 4; };
 template <> struct Op<P_BF16> { static constexpr int CH = 32; static constexpr int QE = 8; };
 
+// Per mode: output tile TH x TW, halo HH x HW (rows x positions), position
+// blocks per wave MB, weight tap-matrices per stage WT, temporal stages KTS.
 template <int MODE> struct Geo;
 template <> struct Geo<CM_S1> {
   static constexpr int WR = 2, TW = 64, TH = 8, HH = TH + 2, HW = TW + 2;
+  static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
 template <> struct Geo<CM_S2> {
   static constexpr int WR = 1, TW = 32, TH = 4, HH = 2 * TH + 1, HW = 2 * TW + 1;
+  static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
 template <> struct Geo<CM_UP> {
   static constexpr int WR = 2, TW = 64, TH = 8, HH = TH / 2 + 2, HW = TW / 2 + 2;
+  static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
+// Polyphase upsample conv: wave w owns output phase (h & 1, w & 1) = (w >> 1, w & 1)
+// of the tile, i.e. 4 source rows x 32 source columns = 8 blocks; a stage holds
+// the 2 x 2 folded taps of all 4 phases.
+template <> struct Geo<CM_UPF> {
+  static constexpr int WR = 0, TW = 64, TH = 8, HH = TH / 2 + 2, HW = TW / 2 + 2;
+  static constexpr int MB = (TH / 2) * (TW / 2 / 16), WT = 16, KTS = 2;
+};
+
+// Output-tile-local position of lane l16 in position block m of a wave.
+template <int MODE>
+__device__ __forceinline__ void out_local(int wave, int m, int l16, int* i, int* j) {
+  using G = Geo<MODE>;
+  if constexpr (MODE == CM_UPF) {
+    *i = 2 * (m >> 1) + (wave >> 1);
+    *j = 2 * ((m & 1) * 16 + l16) + (wave & 1);
+  } else {
+    constexpr int BPR = G::TW / 16;
+    *i = wave * G::WR + m / BPR;
+    *j = (m % BPR) * 16 + l16;
+  }
+}
 
 // LDS row (position) index of output-local (i, j) for tap (kh, kw).
 template <int MODE>
@@ -78,10 +107,16 @@ __device__ __forceinline__ void halo_src(int p, int h0, int w0, int* hs, int* ws
     const int c = (pc < G::TW + 1) ? 2 * pc : 2 * (pc - (G::TW + 1)) + 1;
     *hs = 2 * h0 - 1 + r;
     *ws = 2 * w0 - 1 + c;
-  } else {
+  } else {  // CM_UP, CM_UPF: source rows / columns of the upsampled tile
     *hs = (h0 >> 1) - 1 + r;
     *ws = (w0 >> 1) - 1 + pc;
   }
+}
+
+// 16-byte direct global->LDS load (global_load_lds_dwordx4): lane l of the
+// wave writes LDS address lds_wave_base + 16 l.  lds_wave_base must be uniform.
+__device__ __forceinline__ void lds_dma16(const uint4* g, uint4* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(g, lds_wave_base, 16, 0, 0);
 }
 
 template <int PREC>
@@ -97,28 +132,6 @@ __device__ __forceinline__ void mfma_quad(f32x4& acc, const uint4& wq, const uin
   }
 }
 
-// Prologue on one 16-byte quad: y = silu(x * sc + sh) for QE channels.
-template <int PREC>
-__device__ __forceinline__ uint4 prologue(uint4 v, const float* sc, const float* sh) {
-  if constexpr (PREC == P_BF16) {
-    uint32_t u[4] = {v.x, v.y, v.z, v.w};
-    uint32_t o[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float a = silu_f(fmaf(bf16_lo(u[k]), sc[2 * k], sh[2 * k]));
-      const float b = silu_f(fmaf(bf16_hi(u[k]), sc[2 * k + 1], sh[2 * k + 1]));
-      o[k] = pack_bf16(a, b);
-    }
-    return make_uint4(o[0], o[1], o[2], o[3]);
-  } else {
-    float f[4] = {__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w)};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) f[k] = silu_f(fmaf(f[k], sc[k], sh[k]));
-    return make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
-                      __float_as_uint(f[3]));
-  }
-}
-
 // Map a linear block index to a virtual tile index so that the blocks one XCD
 // receives (hardware dispatches block b to XCD b % 8) are contiguous tiles.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -127,17 +140,21 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + min(x, r) + l;
 }
 
-template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool PRO, bool RESID, bool STATS>
-__global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
+template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS, bool DB>
+__global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch a) {
   using G = Geo<MODE>;
   using O = Op<PREC>;
   constexpr int NT = NB * 16;           // output channels per workgroup
   constexpr int HALO = G::HH * G::HW;   // halo rows (positions)
-  constexpr int BPR = G::TW / 16;       // 16-position blocks per tile row
-  constexpr int MB = G::WR * BPR;       // position blocks per wave
+  constexpr int MB = G::MB;             // position blocks per wave
+  constexpr int HQ = HALO * 4;          // halo quads per stage
+  constexpr int WQ = G::WT * NT * 4;    // weight quads per stage
+  constexpr int NBUF = DB ? 2 : 1;      // LDS buffers (double buffering: 1 workgroup per CU)
+  static_assert(WQ % 64 == 0, "weight stage must be whole waves");
+  static_assert(!DB || IN_KIND == IN_ACT, "double buffering needs asynchronous staging");
 
-  __shared__ uint4 lds_a[HALO * 4];
-  __shared__ uint4 lds_w[9 * NT * 4];
+  __shared__ uint4 lds_a[NBUF][HQ];
+  __shared__ uint4 lds_w[NBUF][WQ];
   __shared__ float red[kWaves][32];
   __shared__ float gmean[32];
 
@@ -164,86 +181,177 @@ __global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
     for (int b = 0; b < NB; ++b) acc[m][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const size_t plane_in = (size_t)a.Hi * a.Wi;
-  const size_t wstage = (size_t)9 * NT * 4;  // uint4 per (kt, chunk) weight stage
-  const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + (size_t)ct * 3 * a.in_chunks * wstage;
+  // Folded weights come in two sets, one per output-frame parity.
+  const int tg = a.go0 + to;  // global output frame
+  const size_t wset = MODE == CM_UPF ? (size_t)ct * 2 + (tg & 1) : (size_t)ct;
+  const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + wset * G::KTS * a.in_chunks * WQ;
+  const int nstages = G::KTS * a.in_chunks;  // stage = (temporal tap, input chunk)
 
-  for (int kt = 0; kt < 3; ++kt) {
-    int ts;
-    if constexpr (MODE == CM_S1) ts = max(to + kt - 2, 0);
-    else if constexpr (MODE == CM_S2) ts = max(2 * to + kt - 2, 0);
-    else ts = (max(to + kt - 2, 0) + 1) >> 1;
+  // Input buffer frame read by temporal tap kt (causal in global frame
+  // numbers: frame 0 repeats for t < 0).
+  auto src_frame = [&](int kt) {
+    int g;
+    if constexpr (MODE == CM_S1) g = max(tg + kt - 2, 0);
+    else if constexpr (MODE == CM_S2) g = max(2 * tg + kt - 2, 0);
+    else if constexpr (MODE == CM_UP) g = (max(tg + kt - 2, 0) + 1) >> 1;
+    else {
+      // even output frame 2j reads source frames j-1 (clamped) and j; odd 2j+1 reads j and j+1
+      const int jt = tg >> 1;
+      g = (tg & 1) ? jt + kt : max(jt - 1 + kt, 0);
+    }
+    return g - a.gi0;
+  };
 
-    for (int ck = 0; ck < a.in_chunks; ++ck) {
-      __syncthreads();
-      // ---- stage the activation halo -----------------------------------
-      if constexpr (IN_KIND == IN_ACT) {
-        const uint4* src = reinterpret_cast<const uint4*>(a.in) +
-                           (((size_t)n * a.Ti + ts) * a.in_chunks + ck) * plane_in * 4;
-        const float* sc = PRO ? a.gn_scale + ((size_t)n * a.Ti + ts) * a.Cin + ck * O::CH : nullptr;
-        const float* sh = PRO ? a.gn_shift + ((size_t)n * a.Ti + ts) * a.Cin + ck * O::CH : nullptr;
-        for (int e = tid; e < HALO * 4; e += kThreads) {
-          const int p = e >> 2, q = e & 3;
-          int hs, ws;
-          halo_src<MODE>(p, h0, w0, &hs, &ws);
-          uint4 val = make_uint4(0, 0, 0, 0);
-          if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
-            val = src[((size_t)hs * a.Wi + ws) * 4 + q];
-            if constexpr (PRO) val = prologue<PREC>(val, sc + q * O::QE, sh + q * O::QE);
-          }
-          lds_a[p * 4 + (q ^ swz(p))] = val;
-        }
-      } else {
-        // uint8 RGB input, x / 127.5 - 1 in channels 0..2 of quad 0, zeros elsewhere
-        const uint8_t* src = reinterpret_cast<const uint8_t*>(a.in) + ((size_t)n * a.Ti + ts) * plane_in * 3;
-        for (int e = tid; e < HALO * 4; e += kThreads) {
-          const int p = e >> 2, q = e & 3;
-          int hs, ws;
-          halo_src<MODE>(p, h0, w0, &hs, &ws);
-          uint4 val = make_uint4(0, 0, 0, 0);
-          if (q == 0 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
-            const uint8_t* px = src + ((size_t)hs * a.Wi + ws) * 3;
-            const float r = (float)px[0] / 127.5f - 1.0f;
-            const float g = (float)px[1] / 127.5f - 1.0f;
-            const float bch = (float)px[2] / 127.5f - 1.0f;
-            if constexpr (PREC == P_BF16) {
-              val = make_uint4(pack_bf16(r, g), pack_bf16(bch, 0.f), 0, 0);
-            } else {
-              val = make_uint4(__float_as_uint(r), __float_as_uint(g), __float_as_uint(bch), 0);
-            }
-          }
-          lds_a[p * 4 + (q ^ swz(p))] = val;
+  // Halo slots this thread's lanes fill are the same in every stage: keep
+  // their in-frame quad offsets (or -1 for the zero padding) in registers.
+  constexpr int NHS = (HQ + kThreads - 1) / kThreads;
+  int hoff[NHS];
+#pragma unroll
+  for (int k = 0; k < NHS; ++k) {
+    const int e = wave * 64 + k * kThreads + lane;
+    hoff[k] = -1;
+    if (e < HQ) {
+      const int p = e >> 2;
+      const int q = (e & 3) ^ swz(p);
+      int hs, ws;
+      halo_src<MODE>(p, h0, w0, &hs, &ws);
+      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) hoff[k] = (hs * a.Wi + ws) * 4 + q;
+    }
+  }
+
+  // Issue the global->LDS transfers of stage st into buffer buf: the 9 taps of
+  // packed weights and the spatial halo, both as direct-to-LDS loads (lane l
+  // of a wave writes 16 bytes at the wave's LDS base + 16 l).  Slot (p, pq) of
+  // the halo holds logical quad pq ^ swz(p) of halo row p; rows outside the
+  // frame are written as zeros (the conv's zero padding).
+  auto issue_async = [&](int st, int buf) {
+    const int kt = st / a.in_chunks, ck = st - kt * a.in_chunks;
+    const uint4* wsrc = wbase + (size_t)st * WQ;
+#pragma unroll
+    for (int base = wave * 64; base < WQ; base += kThreads) lds_dma16(wsrc + base + lane, &lds_w[buf][base]);
+    const uint4* src = reinterpret_cast<const uint4*>(a.in) +
+                       (((size_t)n * a.Ti + src_frame(kt)) * a.in_chunks + ck) * plane_in * 4;
+#pragma unroll
+    for (int k = 0; k < NHS; ++k) {
+      const int base = wave * 64 + k * kThreads;
+      const int e = base + lane;
+      if (e < HQ) {
+        if (hoff[k] >= 0) lds_dma16(src + hoff[k], &lds_a[buf][base]);
+        else lds_a[buf][e] = make_uint4(0, 0, 0, 0);
+      }
+    }
+  };
+
+  // uint8 RGB input (first layer): x / 127.5 - 1 in channels 0..2 of quad 0,
+  // zeros elsewhere; converted in registers, so staged synchronously.
+  auto stage_u8 = [&](int st) {
+    constexpr int NHQ = (HQ + kThreads - 1) / kThreads;
+    const int kt = st / a.in_chunks;
+    const uint4* wsrc = wbase + (size_t)st * WQ;
+#pragma unroll
+    for (int base = wave * 64; base < WQ; base += kThreads) lds_dma16(wsrc + base + lane, &lds_w[0][base]);
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(a.in) + ((size_t)n * a.Ti + src_frame(kt)) * plane_in * 3;
+    uint32_t px[NHQ];
+    uint32_t inb = 0;
+#pragma unroll
+    for (int k = 0; k < NHQ; ++k) {
+      const int e = tid + k * kThreads;
+      px[k] = 0;
+      if (e < HQ && (e & 3) == 0) {
+        int hs, ws;
+        halo_src<MODE>(e >> 2, h0, w0, &hs, &ws);
+        if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
+          const uint8_t* pp = src + ((size_t)hs * a.Wi + ws) * 3;
+          px[k] = (uint32_t)pp[0] | ((uint32_t)pp[1] << 8) | ((uint32_t)pp[2] << 16);
+          inb |= 1u << k;
         }
       }
-      // ---- stage the weights of this (kt, chunk) -------------------------
-      {
-        const uint4* wsrc = wbase + ((size_t)kt * a.in_chunks + ck) * wstage;
-        for (int e = tid; e < 9 * NT * 4; e += kThreads) lds_w[e] = wsrc[e];
+    }
+#pragma unroll
+    for (int k = 0; k < NHQ; ++k) {
+      const int e = tid + k * kThreads;
+      if (e < HQ) {
+        const int p = e >> 2, q = e & 3;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (inb & (1u << k)) {
+          const float r = (float)(px[k] & 0xff) / 127.5f - 1.0f;
+          const float g = (float)((px[k] >> 8) & 0xff) / 127.5f - 1.0f;
+          const float bch = (float)((px[k] >> 16) & 0xff) / 127.5f - 1.0f;
+          if constexpr (PREC == P_BF16) val = make_uint4(pack_bf16(r, g), pack_bf16(bch, 0.f), 0, 0);
+          else val = make_uint4(__float_as_uint(r), __float_as_uint(g), __float_as_uint(bch), 0);
+        }
+        lds_a[0][p * 4 + (q ^ swz(p))] = val;
       }
-      __syncthreads();
+    }
+  };
 
-      // ---- 9 spatial taps of MFMAs --------------------------------------
+  // The 9 spatial taps of one stage: every wave multiplies its MB position
+  // blocks by the NB output-channel blocks.
+  auto compute = [&](int buf) {
+    if constexpr (MODE == CM_UPF) {
+      const int ph = wave >> 1, pw = wave & 1;
+#pragma unroll
+      for (int tap = 0; tap < 4; ++tap) {
+        const int dh = tap >> 1, dw = tap & 1;
+        uint4 wq[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int row = (wave * 4 + tap) * NT + b * 16 + l16;
+          wq[b] = lds_w[buf][row * 4 + (g4 ^ swz(row))];
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const int row = ((m >> 1) + dh + ph) * G::HW + ((m & 1) * 16 + l16 + dw + pw);
+          const uint4 aq = lds_a[buf][row * 4 + (g4 ^ swz(row))];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
+        }
+      }
+      return;
+    }
+    constexpr int BPR = G::TW / 16;
 #pragma unroll 1
-      for (int kh = 0; kh < 3; ++kh) {
+    for (int kh = 0; kh < 3; ++kh) {
 #pragma unroll
-        for (int kw = 0; kw < 3; ++kw) {
-          const int tap = kh * 3 + kw;
-          uint4 wq[NB];
+      for (int kw = 0; kw < 3; ++kw) {
+        const int tap = kh * 3 + kw;
+        uint4 wq[NB];
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const int row = tap * NT + b * 16 + l16;
-            wq[b] = lds_w[row * 4 + (g4 ^ swz(row))];
-          }
+        for (int b = 0; b < NB; ++b) {
+          const int row = tap * NT + b * 16 + l16;
+          wq[b] = lds_w[buf][row * 4 + (g4 ^ swz(row))];
+        }
 #pragma unroll
-          for (int m = 0; m < MB; ++m) {
-            const int i = wave * G::WR + m / BPR;
-            const int j = (m % BPR) * 16 + l16;
-            const int row = act_row<MODE>(i, j, kh, kw);
-            const uint4 aq = lds_a[row * 4 + (g4 ^ swz(row))];
+        for (int m = 0; m < MB; ++m) {
+          const int i = wave * G::WR + m / BPR;
+          const int j = (m % BPR) * 16 + l16;
+          const int row = act_row<MODE>(i, j, kh, kw);
+          const uint4 aq = lds_a[buf][row * 4 + (g4 ^ swz(row))];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
-          }
+          for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
         }
       }
+    }
+  };
+
+  if constexpr (DB) {
+    issue_async(0, 0);
+    for (int st = 0; st < nstages; ++st) {
+      // stage st has landed in buffer st & 1, and every wave is done with
+      // stage st - 1, whose buffer the next transfers overwrite
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (st + 1 < nstages) issue_async(st + 1, (st + 1) & 1);
+      compute(st & 1);
+    }
+  } else {
+    for (int st = 0; st < nstages; ++st) {
+      __syncthreads();
+      if constexpr (IN_KIND == IN_ACT) issue_async(st, 0);
+      else stage_u8(st);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // direct-to-LDS loads have landed
+      __syncthreads();
+      compute(0);
     }
   }
 
@@ -255,8 +363,8 @@ __global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
 
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int i = wave * G::WR + m / BPR;
-    const int j = (m % BPR) * 16 + l16;
+    int i, j;
+    out_local<MODE>(wave, m, l16, &i, &j);
     const int oh = h0 + i, ow = w0 + j;
     const bool valid = (oh < a.Ho) && (ow < a.Wo);
 #pragma unroll
@@ -267,7 +375,7 @@ __global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
       for (int r = 0; r < 4; ++r) v4[r] = acc[m][b][r] + ((c0 + r) < a.Cout ? a.bias[c0 + r] : 0.f);
       if constexpr (OUT_KIND == OUT_ACT) {
         const int chunk = c0 / O::CH, within = c0 % O::CH;
-        const size_t off = (((size_t)n * a.To + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
+        const size_t off = (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
                            ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * (kChunkBytes / O::CH);
         if constexpr (PREC == P_BF16) {
           if (valid) {
@@ -292,7 +400,8 @@ __global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
         }
       } else {
         if (valid) {
-          float* op = reinterpret_cast<float*>(a.out) + (((size_t)n * a.To + to) * plane_out + (size_t)oh * a.Wo + ow) * 3;
+          float* op = reinterpret_cast<float*>(a.out) +
+                      (((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3;
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             if (c0 + r < 3) op[c0 + r] = v4[r];
@@ -335,8 +444,8 @@ __global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
       float qa = 0.f, qb = 0.f;
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
-        const int i = wave * G::WR + m / BPR;
-        const int j = (m % BPR) * 16 + l16;
+        int i, j;
+        out_local<MODE>(wave, m, l16, &i, &j);
         if (h0 + i < a.Ho && w0 + j < a.Wo) {
           const float d0 = acc[m][b][0] - ma, d1 = acc[m][b][1] - ma;
           const float d2 = acc[m][b][2] - mb, d3 = acc[m][b][3] - mb;
@@ -370,44 +479,54 @@ __global__ void __launch_bounds__(kThreads, 2) conv3d_kernel(ConvLaunch a) {
   }
 }
 
-template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool PRO, bool RESID, bool STATS>
+template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS, bool DB = false>
 hipError_t launch_one(const ConvLaunch& a, hipStream_t s) {
   const long long nb = (long long)a.N * a.To * a.tiles_h * a.tiles_w * a.cout_tiles;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((conv3d_kernel<PREC, MODE, NB, IN_KIND, OUT_KIND, PRO, RESID, STATS>),
+  hipLaunchKernelGGL((conv3d_kernel<PREC, MODE, NB, IN_KIND, OUT_KIND, RESID, STATS, DB>),
                      dim3((unsigned)nb), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
+#ifndef TOK_CONV_DB
+#define TOK_CONV_DB 0
+#endif
+constexpr bool kDB = TOK_CONV_DB != 0;
+
 template <int PREC>
 hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   // The configurations the tokenizer uses.
+  const bool res = a.resid != nullptr, st = a.stats != nullptr;
   if (a.in_kind == IN_U8) {
-    if (a.mode == CM_S1 && a.nt == 64 && a.out_kind == OUT_ACT && !a.gn_scale && !a.resid && a.stats)
-      return launch_one<PREC, CM_S1, 4, IN_U8, OUT_ACT, false, false, true>(a, s);
+    if (a.mode == CM_S1 && a.nt == 64 && a.out_kind == OUT_ACT && !res && st)
+      return launch_one<PREC, CM_S1, 4, IN_U8, OUT_ACT, false, true>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.out_kind == OUT_RGB32) {
-    if (a.mode == CM_S1 && a.nt == 16 && !a.gn_scale && !a.resid && !a.stats)
-      return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false, false>(a, s);
+    if (a.mode == CM_S1 && a.nt == 16 && !res && !st)
+      return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false, kDB>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.nt != 64) return hipErrorInvalidValue;
-  const bool pro = a.gn_scale != nullptr, res = a.resid != nullptr, st = a.stats != nullptr;
   if (a.mode == CM_S1) {
-    if (pro && !res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, false, true>(a, s);
-    if (pro && res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, true, true>(a, s);
-    if (pro && res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, true, false>(a, s);
-    if (!pro && !res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, false, false>(a, s);
+    if (!res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
+    if (res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, true, kDB>(a, s);
+    if (res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, false, kDB>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_S2) {
-    if (!pro && !res && !st) return launch_one<PREC, CM_S2, 4, IN_ACT, OUT_ACT, false, false, false>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_S2, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_UP) {
-    if (!pro && !res && !st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, false, false>(a, s);
-    if (!pro && !res && st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, false, true>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
+    if (!res && st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.mode == CM_UPF) {
+    if (!res && !st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
+    if (!res && st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
     return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
@@ -426,23 +545,72 @@ hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
 //   [ct][kt][chunk][kh*3+kw][o (nt)][quad 0..3][QE]   (quads XOR-swizzled by row)
 // where row = tap * nt + o, and chunk covers CH input channels; channels
 // beyond Cin / Cout are zero.  One (ct, kt, chunk) stage is 9 * nt * 64 bytes.
-size_t packed_conv_elems(int Cout, int Cin, int prec, int* nt_out) {
+// Polyphase upsample layout (CM_UPF), per ct and output-frame parity pt:
+//   [ct][pt][dt][chunk][phase][dh*2+dw][o][quad][QE], row = (phase*4 + tap) * nt + o,
+// holding the folded kernel: along each of t, h, w a nearest-x2 upsample
+// followed by a 3-tap kernel is, for output parity 0, tap 0 on source offset
+// -1 and taps 1+2 on offset 0; for parity 1, taps 0+1 on offset 0 and tap 2 on
+// offset +1.
+namespace {
+int fold_lo(int parity, int d) { return parity == 0 ? (d == 0 ? 0 : 1) : (d == 0 ? 0 : 2); }
+int fold_hi(int parity, int d) { return parity == 0 ? (d == 0 ? 0 : 2) : (d == 0 ? 1 : 2); }
+
+void store_elem(void* dst, size_t e, float v, int prec) {
+  if (prec == P_BF16) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    reinterpret_cast<uint16_t*>(dst)[e] = (uint16_t)(u >> 16);
+  } else {
+    reinterpret_cast<float*>(dst)[e] = v;
+  }
+}
+}  // namespace
+
+size_t packed_conv_elems(int Cout, int Cin, int prec, int mode, int* nt_out) {
   const int CH = prec == P_BF16 ? 32 : 16;
   const int nt = Cout >= 64 ? 64 : 16;
   const int tiles = (Cout + nt - 1) / nt;
   const int chunks = (Cin + CH - 1) / CH;
   if (nt_out) *nt_out = nt;
+  if (mode == CM_UPF) return (size_t)tiles * 2 * 2 * chunks * 16 * nt * CH;
   return (size_t)tiles * 3 * chunks * 9 * nt * CH;
 }
 
-void pack_conv_weights(const float* w, int Cout, int Cin, int prec, void* dst) {
+void pack_conv_weights(const float* w, int Cout, int Cin, int prec, int mode, void* dst) {
   const int CH = prec == P_BF16 ? 32 : 16;
   const int QE = CH / 4;
   int nt;
-  const size_t total = packed_conv_elems(Cout, Cin, prec, &nt);
+  packed_conv_elems(Cout, Cin, prec, mode, &nt);
   const int tiles = (Cout + nt - 1) / nt;
   const int chunks = (Cin + CH - 1) / CH;
+  auto W = [&](int co, int ci, int kt, int kh, int kw) -> float {
+    if (co >= Cout || ci >= Cin) return 0.f;
+    return w[((((size_t)co * Cin + ci) * 3 + kt) * 3 + kh) * 3 + kw];
+  };
   size_t e = 0;
+  if (mode == CM_UPF) {
+    for (int ct = 0; ct < tiles; ++ct)
+      for (int pt = 0; pt < 2; ++pt)
+        for (int dt = 0; dt < 2; ++dt)
+          for (int ck = 0; ck < chunks; ++ck)
+            for (int phase = 0; phase < 4; ++phase)
+              for (int tap = 0; tap < 4; ++tap)
+                for (int o = 0; o < nt; ++o)
+                  for (int pq = 0; pq < 4; ++pq)
+                    for (int x = 0; x < QE; ++x, ++e) {
+                      const int row = (phase * 4 + tap) * nt + o;
+                      const int q = pq ^ swz(row);
+                      const int co = ct * nt + o, ci = ck * CH + q * QE + x;
+                      const int ph = phase >> 1, pw = phase & 1, dh = tap >> 1, dw = tap & 1;
+                      float v = 0.f;
+                      for (int kt = fold_lo(pt, dt); kt <= fold_hi(pt, dt); ++kt)
+                        for (int kh = fold_lo(ph, dh); kh <= fold_hi(ph, dh); ++kh)
+                          for (int kw = fold_lo(pw, dw); kw <= fold_hi(pw, dw); ++kw) v += W(co, ci, kt, kh, kw);
+                      store_elem(dst, e, v, prec);
+                    }
+    return;
+  }
   for (int ct = 0; ct < tiles; ++ct)
     for (int kt = 0; kt < 3; ++kt)
       for (int ck = 0; ck < chunks; ++ck)
@@ -451,22 +619,9 @@ void pack_conv_weights(const float* w, int Cout, int Cin, int prec, void* dst) {
             for (int pq = 0; pq < 4; ++pq)
               for (int x = 0; x < QE; ++x, ++e) {
                 const int row = tap * nt + o;
-                const int q = pq ^ ((row >> 1) & 3);  // logical quad stored at physical quad pq
-                const int co = ct * nt + o;
-                const int ci = ck * CH + q * QE + x;
-                const int kh = tap / 3, kw = tap % 3;
-                float v = 0.f;
-                if (co < Cout && ci < Cin) v = w[((((size_t)co * Cin + ci) * 3 + kt) * 3 + kh) * 3 + kw];
-                if (prec == P_BF16) {
-                  uint32_t u;
-                  __builtin_memcpy(&u, &v, 4);
-                  u += 0x7fffu + ((u >> 16) & 1u);
-                  reinterpret_cast<uint16_t*>(dst)[e] = (uint16_t)(u >> 16);
-                } else {
-                  reinterpret_cast<float*>(dst)[e] = v;
-                }
+                const int q = pq ^ swz(row);  // logical quad stored at physical quad pq
+                store_elem(dst, e, W(ct * nt + o, ck * CH + q * QE + x, kt, tap / 3, tap % 3), prec);
               }
-  (void)total;
 }
 
 }  // namespace tok

@@ -61,6 +61,62 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
 }
 
 // ---------------------------------------------------------------------------
+// GroupNorm apply + SiLU, elementwise over a level-0 tensor (64 channels).
+// blockIdx.y = frame * chunks + chunk; every thread handles kItems 16-byte
+// quads of that plane, kThreads apart, so each load / store instruction is
+// fully coalesced and all quads of a thread share one channel set.
+// ---------------------------------------------------------------------------
+constexpr int kActItems = 4;
+
+template <int PREC>
+__global__ void __launch_bounds__(256) gn_act_kernel(const uint4* in, int in_Tb, int in_f0,
+                                                      uint4* out, int out_Tb, int out_f0,  // may alias (in place)
+                                                      int F, int HW, const float* __restrict__ scale,
+                                                      const float* __restrict__ shift) {
+  constexpr int CH = PREC == P_BF16 ? 32 : 16;
+  constexpr int QE = CH / 4;
+  constexpr int CHUNKS = 64 / CH;
+  const int frame = blockIdx.y / CHUNKS, ck = blockIdx.y % CHUNKS;  // frame = n * F + f
+  const int n = frame / F, f = frame % F;
+  const size_t fi = ((size_t)n * in_Tb + in_f0 + f) * CHUNKS + ck;    // input (frame, chunk) plane
+  const size_t fo = ((size_t)n * out_Tb + out_f0 + f) * CHUNKS + ck;  // output plane
+  const size_t plane = (size_t)HW * 4;  // quads per (frame, chunk)
+  const size_t q0 = (size_t)blockIdx.x * (256 * kActItems) + threadIdx.x;
+  const int c0 = ck * CH + (threadIdx.x & 3) * QE;
+  float sc[QE], sh[QE];
+#pragma unroll
+  for (int c = 0; c < QE; ++c) {
+    sc[c] = scale[(size_t)frame * 64 + c0 + c];
+    sh[c] = shift[(size_t)frame * 64 + c0 + c];
+  }
+  const uint4* src = in + fi * plane;
+  uint4* dst = out + fo * plane;
+  uint4 v[kActItems];
+#pragma unroll
+  for (int k = 0; k < kActItems; ++k) {
+    const size_t q = q0 + (size_t)k * 256;
+    if (q < plane) v[k] = src[q];
+  }
+#pragma unroll
+  for (int k = 0; k < kActItems; ++k) {
+    const size_t q = q0 + (size_t)k * 256;
+    if (q >= plane) continue;
+    uint32_t u[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+    uint32_t o[4];
+    if constexpr (PREC == P_BF16) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        o[j] = pack_bf16(silu_f(fmaf(bf16_lo(u[j]), sc[2 * j], sh[2 * j])),
+                         silu_f(fmaf(bf16_hi(u[j]), sc[2 * j + 1], sh[2 * j + 1])));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o[j] = __float_as_uint(silu_f(fmaf(__uint_as_float(u[j]), sc[j], sh[j])));
+    }
+    dst[q] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FSQ (Mentzer et al.): b = tanh(z + s) h - o; q = rint(b) (half to even);
 // codes = q / floor(L/2); idx = sum (q + floor(L/2)) * basis.
 // ---------------------------------------------------------------------------
@@ -93,20 +149,25 @@ __device__ __forceinline__ uint8_t keep_bit(const DropArgs& d, int n, int t, int
 // Level-2 activations (chunked, 128 ch) -> z (6) -> FSQ -> mask.  One thread
 // per token; the 6 x 128 projection lives in LDS.
 template <int PREC>
-__global__ void __launch_bounds__(256) proj_fsq_kernel(const void* __restrict__ act, int N, int T2, int H2,
-                                                        int W2, int in_chunks, const float* __restrict__ wp,
-                                                        const float* __restrict__ bp, FsqConst fc, DropArgs d,
-                                                        float* __restrict__ z, float* __restrict__ codes,
-                                                        int32_t* __restrict__ idx, uint8_t* __restrict__ keep) {
+__global__ void __launch_bounds__(256) proj_fsq_kernel(const void* __restrict__ act, int N, int Tb, int f0, int F,
+                                                        int T2, int t0, int H2, int W2, int in_chunks,
+                                                        const float* __restrict__ wp, const float* __restrict__ bp,
+                                                        FsqConst fc, DropArgs d, float* __restrict__ z,
+                                                        float* __restrict__ codes, int32_t* __restrict__ idx,
+                                                        uint8_t* __restrict__ keep) {
   constexpr int CH = PREC == P_BF16 ? 32 : 16;
   __shared__ float w[6 * 128];
   for (int e = threadIdx.x; e < 6 * 128; e += blockDim.x) w[e] = wp[e];
   __syncthreads();
   const size_t HW = (size_t)H2 * W2;
-  const size_t ntok = (size_t)N * T2 * HW;
-  const size_t tok = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tok >= ntok) return;
-  const size_t frame = tok / HW, hw = tok % HW;
+  const size_t ntok = (size_t)N * F * HW;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ntok) return;
+  const size_t nf = gid / HW, hw = gid % HW;
+  const int n = (int)(nf / F), f = (int)(nf % F);
+  const int t = t0 + f;                                   // global latent frame
+  const size_t frame = (size_t)n * Tb + f0 + f;           // activation buffer frame
+  const size_t tok = ((size_t)n * T2 + t) * HW + hw;      // dense output token
   float acc[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) acc[c] = bp[c];
@@ -139,7 +200,6 @@ __global__ void __launch_bounds__(256) proj_fsq_kernel(const void* __restrict__ 
   float cd[6];
   int id;
   fsq6(acc, fc, cd, &id);
-  const int n = (int)(frame / T2), t = (int)(frame % T2);
   const int h = (int)(hw / W2), ww = (int)(hw % W2);
   const uint8_t k = keep_bit(d, n, t, h, ww, T2, H2, W2);
   if (z) {
@@ -191,20 +251,25 @@ __global__ void __launch_bounds__(256) drop_kernel(DropArgs d, float* __restrict
 
 // codes (6) -> 128 channels; one thread per (token, chunk) writes 64 bytes.
 template <int PREC>
-__global__ void __launch_bounds__(256) proj_in_kernel(const float* __restrict__ codes, size_t ntok,
-                                                       const float* __restrict__ wpin, const float* __restrict__ bpin,
-                                                       void* __restrict__ out, int out_chunks, int HW) {
+__global__ void __launch_bounds__(256) proj_in_kernel(const float* __restrict__ codes, int N, int T2, int t0, int F,
+                                                       int HW, const float* __restrict__ wpin,
+                                                       const float* __restrict__ bpin, void* __restrict__ out,
+                                                       int out_chunks, int Tb, int f0) {
   constexpr int CH = PREC == P_BF16 ? 32 : 16;
   __shared__ float w[128 * 6];
   __shared__ float bsh[128];
   for (int e = threadIdx.x; e < 128 * 6; e += blockDim.x) w[e] = wpin[e];
   for (int e = threadIdx.x; e < 128; e += blockDim.x) bsh[e] = bpin[e];
   __syncthreads();
+  const size_t ntok = (size_t)N * F * HW;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= ntok * out_chunks) return;
-  const size_t tok = gid / out_chunks;
+  const size_t lt = gid / out_chunks;  // (n, f, hw)
   const int ck = (int)(gid % out_chunks);
-  const size_t frame = tok / HW, hw = tok % HW;
+  const size_t nf = lt / HW, hw = lt % HW;
+  const int n = (int)(nf / F), f = (int)(nf % F);
+  const size_t tok = ((size_t)n * T2 + t0 + f) * HW + hw;  // dense input token
+  const size_t frame = (size_t)n * Tb + f0 + f;            // output buffer frame
   float c6[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) c6[c] = codes[tok * 6 + c];
@@ -242,16 +307,32 @@ hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const 
   return hipGetLastError();
 }
 
-hipError_t launch_proj_fsq(const void* act, int prec, int N, int T2, int H2, int W2, int in_chunks,
-                           const float* wp, const float* bp, const FsqConst& fc, const DropArgs& d, float* z,
-                           float* codes, int32_t* idx, uint8_t* keep, hipStream_t s) {
-  const size_t ntok = (size_t)N * T2 * H2 * W2;
+hipError_t launch_gn_act(const void* in, int in_Tb, int in_f0, void* out, int out_Tb, int out_f0, int prec, int N,
+                         int F, int HW, const float* scale, const float* shift, hipStream_t s) {
+  const int chunks = prec == P_BF16 ? 2 : 4;
+  const long long frames = (long long)N * F;
+  if (frames * chunks > 65535 || F < 1 || in_f0 < 0 || in_f0 + F > in_Tb || out_f0 < 0 || out_f0 + F > out_Tb)
+    return hipErrorInvalidValue;
+  const dim3 grid(blocks_for((size_t)HW * 4, 256 * kActItems), (unsigned)(frames * chunks));
   if (prec == P_BF16)
-    hipLaunchKernelGGL(proj_fsq_kernel<P_BF16>, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, act, N, T2, H2, W2,
-                       in_chunks, wp, bp, fc, d, z, codes, idx, keep);
+    hipLaunchKernelGGL(gn_act_kernel<P_BF16>, grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(in), in_Tb, in_f0,
+                       reinterpret_cast<uint4*>(out), out_Tb, out_f0, F, HW, scale, shift);
   else
-    hipLaunchKernelGGL(proj_fsq_kernel<P_F32>, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, act, N, T2, H2, W2,
-                       in_chunks, wp, bp, fc, d, z, codes, idx, keep);
+    hipLaunchKernelGGL(gn_act_kernel<P_F32>, grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(in), in_Tb, in_f0,
+                       reinterpret_cast<uint4*>(out), out_Tb, out_f0, F, HW, scale, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_proj_fsq(const void* act, int prec, int N, int Tb, int f0, int F, int T2, int t0, int H2, int W2,
+                           int in_chunks, const float* wp, const float* bp, const FsqConst& fc, const DropArgs& d,
+                           float* z, float* codes, int32_t* idx, uint8_t* keep, hipStream_t s) {
+  const size_t ntok = (size_t)N * F * H2 * W2;
+  if (prec == P_BF16)
+    hipLaunchKernelGGL(proj_fsq_kernel<P_BF16>, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, act, N, Tb, f0, F, T2,
+                       t0, H2, W2, in_chunks, wp, bp, fc, d, z, codes, idx, keep);
+  else
+    hipLaunchKernelGGL(proj_fsq_kernel<P_F32>, dim3(blocks_for(ntok, 256)), dim3(256), 0, s, act, N, Tb, f0, F, T2,
+                       t0, H2, W2, in_chunks, wp, bp, fc, d, z, codes, idx, keep);
   return hipGetLastError();
 }
 
@@ -269,15 +350,15 @@ hipError_t launch_drop(const DropArgs& d, float* codes, uint8_t* keep, int N, in
   return hipGetLastError();
 }
 
-hipError_t launch_proj_in(const float* codes, size_t ntok, const float* w, const float* b, int prec, void* out,
-                          int out_chunks, int HW, hipStream_t s) {
-  const size_t n = ntok * out_chunks;
+hipError_t launch_proj_in(const float* codes, int N, int T2, int t0, int F, int HW, const float* w, const float* b,
+                          int prec, void* out, int out_chunks, int Tb, int f0, hipStream_t s) {
+  const size_t n = (size_t)N * F * HW * out_chunks;
   if (prec == P_BF16)
-    hipLaunchKernelGGL(proj_in_kernel<P_BF16>, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, ntok, w, b, out,
-                       out_chunks, HW);
+    hipLaunchKernelGGL(proj_in_kernel<P_BF16>, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, N, T2, t0, F, HW, w,
+                       b, out, out_chunks, Tb, f0);
   else
-    hipLaunchKernelGGL(proj_in_kernel<P_F32>, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, ntok, w, b, out,
-                       out_chunks, HW);
+    hipLaunchKernelGGL(proj_in_kernel<P_F32>, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, N, T2, t0, F, HW, w,
+                       b, out, out_chunks, Tb, f0);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // C ABI of libtok.so: model packing, workspace planning and the launch
 // sequences of encode / decode (see include/tok.h for the contract).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -67,6 +68,13 @@ size_t blob_count() {
   return n;
 }
 
+// Addressing mode of each 3x3x3 layer.
+int conv_mode(int l) {
+  if (l == L_DOWN1 || l == L_DOWN2) return CM_S2;
+  if (l == L_UP2 || l == L_UP1) return CM_UPF;
+  return CM_S1;
+}
+
 constexpr float kGnEps = 1e-6f;
 const int kLevels[6] = {8, 8, 8, 5, 5, 5};
 
@@ -128,23 +136,50 @@ bool make_dims(int N, int T, int H, int W, Dims* d) {
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workspace plan for processing a clip in causal temporal chunks of CL latent
+// frames (CL = T2: the whole clip at once).  Chunk [L0, L1) of latent frames
+// covers level-0 frames [max(4 L0 - 3, 0), 4 L1 - 4], level-1 frames
+// [max(2 L0 - 1, 0), 2 L1 - 2] and latent frames [L0, L1 - 1].  Every layer's
+// input buffer keeps the last frames of the previous chunk in front of the
+// current ones (2 for a stride-1 conv, 1 for a stride-2 or upsampling conv),
+// which is all a causal k=3 layer reads from the past, so chunked and
+// whole-clip processing compute the same values.
+constexpr int kCache0 = 2, kCache1 = 1, kCache2 = 1;
+
 struct Plan {
-  size_t l0, l1, l2, stats, scsh;
-  size_t off_l0a, off_l0b, off_l1, off_l2, off_stats, off_sc, off_sh, total;
+  int CL, F0max, F1max, Tb0, Tb1, Tb2;
+  size_t l0, l0c, cache, l1, l2, stats, scsh;
+  size_t off_l0a, off_l0b, off_l0c, off_cache, off_l1, off_l2, off_stats, off_sc, off_sh, total;
 };
 
-Plan make_plan(const Dims& d, int prec) {
+// The four residual-block convs of one level-0 stack share the scratch
+// buffers B (conv input, with cache frames) and C (first conv output); when
+// chunking, each conv's input cache is saved after it runs and restored before
+// it runs in the next chunk, from its own slot of 2 frames per clip.
+constexpr int kRbCaches = 4;
+
+Plan make_plan(const Dims& d, int prec, int CL) {
   const size_t es = prec == P_BF16 ? 2 : 4;
   Plan p;
-  p.l0 = align256((size_t)d.N * d.T * d.H * d.W * 64 * es);
-  p.l1 = align256((size_t)d.N * d.T1 * d.H1 * d.W1 * 128 * es);
-  p.l2 = align256((size_t)d.N * d.T2 * d.H2 * d.W2 * 128 * es);
+  p.CL = CL;
+  p.F0max = CL >= d.T2 ? d.T : 4 * CL;
+  p.F1max = CL >= d.T2 ? d.T1 : 2 * CL;
+  p.Tb0 = kCache0 + p.F0max;
+  p.Tb1 = kCache1 + p.F1max;
+  p.Tb2 = kCache2 + CL;
+  p.l0 = align256((size_t)d.N * p.Tb0 * d.H * d.W * 64 * es);
+  p.l0c = align256((size_t)d.N * p.F0max * d.H * d.W * 64 * es);
+  p.cache = CL >= d.T2 ? 0 : align256((size_t)kRbCaches * d.N * kCache0 * d.H * d.W * 64 * es);
+  p.l1 = align256((size_t)d.N * p.Tb1 * d.H1 * d.W1 * 128 * es);
+  p.l2 = align256((size_t)d.N * p.Tb2 * d.H2 * d.W2 * 128 * es);
   const size_t tiles0 = (size_t)cdiv(d.H, 8) * cdiv(d.W, 64);
-  p.stats = align256((size_t)d.N * d.T * tiles0 * 32 * sizeof(float4));
-  p.scsh = align256((size_t)d.N * d.T * 64 * sizeof(float));
+  p.stats = align256((size_t)d.N * p.F0max * tiles0 * 32 * sizeof(float4));
+  p.scsh = align256((size_t)d.N * p.F0max * 64 * sizeof(float));
   size_t o = 0;
   p.off_l0a = o; o += p.l0;
   p.off_l0b = o; o += p.l0;
+  p.off_l0c = o; o += p.l0c;
+  p.off_cache = o; o += p.cache;
   p.off_l1 = o; o += p.l1;
   p.off_l2 = o; o += p.l2;
   p.off_stats = o; o += p.stats;
@@ -154,11 +189,24 @@ Plan make_plan(const Dims& d, int prec) {
   return p;
 }
 
+// Largest chunk size whose plan fits ws_bytes: the whole clip, else one
+// latent frame per chunk; 0 if neither fits.
+int choose_chunk(const Dims& d, int prec, size_t ws_bytes, Plan* out) {
+  Plan p = make_plan(d, prec, d.T2);
+  if (p.total <= ws_bytes) { *out = p; return d.T2; }
+  p = make_plan(d, prec, 1);
+  if (p.total <= ws_bytes) { *out = p; return 1; }
+  *out = p;
+  return 0;
+}
+
 struct Ws {
   char* base;
   Plan p;
   void* l0a() const { return base + p.off_l0a; }
   void* l0b() const { return base + p.off_l0b; }
+  void* l0c() const { return base + p.off_l0c; }
+  char* cache(int k) const { return base + p.off_cache + (size_t)k * (p.cache / kRbCaches); }
   void* l1() const { return base + p.off_l1; }
   void* l2() const { return base + p.off_l2; }
   float4* stats() const { return reinterpret_cast<float4*>(base + p.off_stats); }
@@ -166,12 +214,19 @@ struct Ws {
   float* sh() const { return reinterpret_cast<float*>(base + p.off_sh); }
 };
 
+// A window of frames in a buffer: Tb frames per clip, buffer frame 0 is
+// global frame g0, the current chunk occupies [first, first + count).
+struct Win {
+  int Tb, g0, first, count;
+};
+
 constexpr int K_GN_FINAL = 16;
-constexpr int K_IDS = 17;
+constexpr int K_GN_ACT = 17;
+constexpr int K_IDS = 18;
 const char* kKernelNames[K_IDS] = {
     "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
     "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
-    "dec.rb2.b", "dec.conv_out", "gn_finalize"};
+    "dec.rb2.b", "dec.conv_out", "gn_finalize", "gn_silu"};
 
 // Records an event pair around the launches made while it is alive (profiling only).
 struct Timed {
@@ -192,18 +247,19 @@ struct Timed {
   }
 };
 
-// Generic conv launch helper.
-tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_kind, int N, int Ti, int Hi,
-                int Wi, int Cin, void* out, int out_kind, int To, int Ho, int Wo, const float* sc,
-                const float* sh, const void* resid, float4* stats, hipStream_t s) {
+// Conv launch: reads the whole input buffer `iw` (its frames are addressed
+// through their global numbers) and writes the window `ow` of the output.
+tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_kind, int N, const Win& iw, int Hi,
+                int Wi, int Cin, void* out, int out_kind, const Win& ow, int Ho, int Wo, const void* resid,
+                float4* stats, hipStream_t s) {
   ConvLaunch a;
   std::memset(&a, 0, sizeof(a));
   const int CH = m->prec == P_BF16 ? 32 : 16;
   a.in = in;
-  a.N = N; a.Ti = Ti; a.Hi = Hi; a.Wi = Wi;
+  a.N = N; a.Ti = iw.Tb; a.Hi = Hi; a.Wi = Wi;
+  a.gi0 = iw.g0;
   a.in_chunks = cdiv(Cin, CH);
   a.Cin = Cin;
-  a.gn_scale = sc; a.gn_shift = sh;
   a.wpk = m->wpk[layer];
   a.bias = m->bias[layer];
   a.Cout = kConv[layer].cout;
@@ -211,7 +267,8 @@ tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_
   a.cout_tiles = cdiv(a.Cout, a.nt);
   a.out = out;
   a.resid = resid;
-  a.To = To; a.Ho = Ho; a.Wo = Wo;
+  a.To = ow.count; a.Ho = Ho; a.Wo = Wo;
+  a.To_buf = ow.Tb; a.out_f0 = ow.first; a.go0 = ow.g0 + ow.first;
   a.out_chunks = cdiv(a.Cout, CH);
   a.stats = stats;
   int th, tw;
@@ -225,11 +282,22 @@ tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_
   return TOK_OK;
 }
 
-tok_status gn_final(const tok_model* m, int norm, const Ws& w, int frames, int Ho, int Wo, hipStream_t s) {
+// GroupNorm `norm` + SiLU of the chunk frames of level-0 buffer `in` (whose
+// per-tile statistics the producing conv left in the stats buffer) into the
+// same frames of `out`.
+tok_status gn_silu(const tok_model* m, int norm, const Ws& w, int N, const void* in, const Win& iw, void* out,
+                   const Win& ow, int Ho, int Wo, hipStream_t s) {
   const int tiles = cdiv(Ho, 8) * cdiv(Wo, 64);
-  Timed tm(m, K_GN_FINAL, s);
-  const hipError_t e = launch_gn_finalize(w.stats(), frames, tiles, m->gamma[norm], m->beta[norm], kGnEps, w.sc(), w.sh(), s);
-  if (e != hipSuccess) return fail(TOK_EDEVICE, std::string("gn_finalize: ") + hipGetErrorString(e));
+  {
+    Timed tm(m, K_GN_FINAL, s);
+    const hipError_t e = launch_gn_finalize(w.stats(), N * iw.count, tiles, m->gamma[norm], m->beta[norm], kGnEps,
+                                            w.sc(), w.sh(), s);
+    if (e != hipSuccess) return fail(TOK_EDEVICE, std::string("gn_finalize: ") + hipGetErrorString(e));
+  }
+  Timed tm(m, K_GN_ACT, s);
+  const hipError_t e = launch_gn_act(in, iw.Tb, iw.first, out, ow.Tb, ow.first, m->prec, N, iw.count, Ho * Wo,
+                                     w.sc(), w.sh(), s);
+  if (e != hipSuccess) return fail(TOK_EDEVICE, std::string("gn_act: ") + hipGetErrorString(e));
   return TOK_OK;
 }
 
@@ -239,26 +307,85 @@ tok_status gn_final(const tok_model* m, int norm, const Ws& w, int frames, int H
     if (s_ != TOK_OK) return s_;   \
   } while (0)
 
-// Two residual blocks at level 0, in place on buffer A (B is scratch).
-// Entry: A holds the block input and (sc, sh) hold GN_a of the first block.
+// Copy `frames` frames per clip between a buffer window position and a cache
+// slot (dir > 0: buffer -> cache, else cache -> buffer).
+tok_status cache_copy(char* buf, int Tb, int first, char* cache, int frames, int N, size_t frame_bytes, int dir,
+                      hipStream_t s) {
+  for (int n = 0; n < N; ++n) {
+    char* b = buf + ((size_t)n * Tb + first) * frame_bytes;
+    char* c = cache + (size_t)n * frames * frame_bytes;
+    TOK_HIP(hipMemcpyAsync(dir > 0 ? c : b, dir > 0 ? b : c, (size_t)frames * frame_bytes, hipMemcpyDeviceToDevice,
+                           s));
+  }
+  return TOK_OK;
+}
+
+// Two residual blocks at level 0 on the chunk window `win`, in place on
+// buffer A; B holds each conv's input (cache frames in front of the chunk),
+// C the first conv's output (chunk frames only).  Entry: A holds the block
+// input and the stats buffer its GroupNorm partials.
+//   B = silu(gn_a(A)); C = conv_a(B) (+stats); B = silu(gn_b(C)); A = A + conv_b(B) (+stats)
+// `chunked`: restore / save each conv's input cache around it.
 tok_status resblocks(const tok_model* m, int first_layer, int first_norm, const Ws& w, const Dims& d,
-                     bool last_stats, hipStream_t s) {
-  const int N = d.N, T = d.T, H = d.H, W = d.W;
+                     const Win& win, bool last_stats, bool chunked, int chunk_index, hipStream_t s) {
+  const int N = d.N, H = d.H, W = d.W;
+  const size_t fb = (size_t)H * W * 64 * (m->prec == P_BF16 ? 2 : 4);
+  const Win cw{w.p.F0max, win.g0 + win.first, 0, win.count};  // C: chunk frames only
+  char* B = static_cast<char*>(w.l0b());
+  auto restore = [&](int k) -> tok_status {
+    if (!chunked || chunk_index == 0) return TOK_OK;
+    return cache_copy(B, win.Tb, win.first - kCache0, w.cache(k), kCache0, N, fb, -1, s);
+  };
+  auto save = [&](int k) -> tok_status {
+    if (!chunked) return TOK_OK;
+    return cache_copy(B, win.Tb, win.first + win.count - kCache0, w.cache(k), kCache0, N, fb, +1, s);
+  };
   for (int r = 0; r < 2; ++r) {
     const int la = first_layer + 2 * r, lb = la + 1;
     const int na = first_norm + 2 * r, nb = na + 1;
-    (void)na;
-    // unit a: B = conv_a(silu(gn_a(A)))   (+ stats for gn_b)
-    TOK_TRY(conv(m, la, CM_S1, w.l0a(), IN_ACT, N, T, H, W, 64, w.l0b(), OUT_ACT, T, H, W, w.sc(), w.sh(), nullptr,
-                 w.stats(), s));
-    TOK_TRY(gn_final(m, nb, w, N * T, H, W, s));
-    // unit b: A = A + conv_b(silu(gn_b(B)))   (+ stats for the next block's gn_a)
+    TOK_TRY(gn_silu(m, na, w, N, w.l0a(), win, w.l0b(), win, H, W, s));
+    TOK_TRY(restore(2 * r));
+    TOK_TRY(conv(m, la, CM_S1, w.l0b(), IN_ACT, N, win, H, W, 64, w.l0c(), OUT_ACT, cw, H, W, nullptr, w.stats(), s));
+    TOK_TRY(save(2 * r));
+    TOK_TRY(gn_silu(m, nb, w, N, w.l0c(), cw, w.l0b(), win, H, W, s));
+    TOK_TRY(restore(2 * r + 1));
     const bool stats = (r == 0) || last_stats;
-    TOK_TRY(conv(m, lb, CM_S1, w.l0b(), IN_ACT, N, T, H, W, 64, w.l0a(), OUT_ACT, T, H, W, w.sc(), w.sh(), w.l0a(),
+    TOK_TRY(conv(m, lb, CM_S1, w.l0b(), IN_ACT, N, win, H, W, 64, w.l0a(), OUT_ACT, win, H, W, w.l0a(),
                  stats ? w.stats() : nullptr, s));
-    if (r == 0) TOK_TRY(gn_final(m, first_norm + 2, w, N * T, H, W, s));
+    TOK_TRY(save(2 * r + 1));
   }
   return TOK_OK;
+}
+
+// Move the last `cache` frames of the chunk window to the front of the buffer
+// (frames first + count - cache .. first + count - 1 -> first - cache ..),
+// ready for the next chunk.  Frame by frame in increasing order, which is safe
+// for overlapping ranges because the destination precedes the source.
+tok_status shift_cache(void* buf, const Win& win, int N, size_t frame_bytes, int cache, hipStream_t s) {
+  char* b = static_cast<char*>(buf);
+  for (int n = 0; n < N; ++n)
+    for (int j = 0; j < cache; ++j) {
+      const int src = win.first + win.count - cache + j, dst = win.first - cache + j;
+      if (src == dst) continue;
+      char* clip = b + (size_t)n * win.Tb * frame_bytes;
+      TOK_HIP(hipMemcpyAsync(clip + (size_t)dst * frame_bytes, clip + (size_t)src * frame_bytes, frame_bytes,
+                             hipMemcpyDeviceToDevice, s));
+    }
+  return TOK_OK;
+}
+
+struct ChunkWins {
+  Win l0, l1, l2;  // level-0, level-1, level-2 windows of chunk [L0, L1)
+};
+
+ChunkWins chunk_windows(const Plan& p, int L0, int L1) {
+  const int a0 = std::max(4 * L0 - 3, 0), b0 = 4 * L1 - 4;
+  const int a1 = std::max(2 * L0 - 1, 0), b1 = 2 * L1 - 2;
+  ChunkWins c;
+  c.l0 = Win{p.Tb0, a0 - kCache0, kCache0, b0 - a0 + 1};
+  c.l1 = Win{p.Tb1, a1 - kCache1, kCache1, b1 - a1 + 1};
+  c.l2 = Win{p.Tb2, L0 - kCache2, kCache2, L1 - L0};
+  return c;
 }
 
 bool valid_drop(const tok_drop_desc* dd) {
@@ -365,7 +492,7 @@ tok_status tok_model_create(const float* host_weights, size_t n_floats, tok_prec
     const ConvSpec& c = kConv[l];
     if (c.k == 3) {
       conv_off[l] = off;
-      off = align256(off + packed_conv_elems(c.cout, c.cin, P, &nt[l]) * es);
+      off = align256(off + packed_conv_elems(c.cout, c.cin, P, conv_mode(l), &nt[l]) * es);
     } else {
       w1_off[l] = off;
       off = align256(off + (size_t)c.cout * c.cin * 4);
@@ -380,7 +507,7 @@ tok_status tok_model_create(const float* host_weights, size_t n_floats, tok_prec
   std::vector<char> host(off, 0);
   for (int l = 0; l < L_COUNT; ++l) {
     const ConvSpec& c = kConv[l];
-    if (c.k == 3) pack_conv_weights(src_w[l], c.cout, c.cin, P, host.data() + conv_off[l]);
+    if (c.k == 3) pack_conv_weights(src_w[l], c.cout, c.cin, P, conv_mode(l), host.data() + conv_off[l]);
     else std::memcpy(host.data() + w1_off[l], src_w[l], (size_t)c.cout * c.cin * 4);
     std::memcpy(host.data() + bias_off[l], src_b[l], (size_t)c.cout * 4);
   }
@@ -438,10 +565,11 @@ void tok_model_destroy(tok_model* m) {
 
 tok_status tok_workspace_size(const tok_model* m, int N, int T, int H, int W, int what, size_t* bytes) {
   if (!m || !bytes) return fail(TOK_EINVAL, "null argument");
-  if (what < TOK_WS_ENCODE || what > TOK_WS_ROUNDTRIP) return fail(TOK_EINVAL, "bad workspace kind");
+  const int kind = what & ~TOK_WS_STREAM;
+  if (kind < TOK_WS_ENCODE || kind > TOK_WS_ROUNDTRIP) return fail(TOK_EINVAL, "bad workspace kind");
   Dims d;
   if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
-  *bytes = make_plan(d, m->prec).total;
+  *bytes = make_plan(d, m->prec, (what & TOK_WS_STREAM) ? 1 : d.T2).total;
   return TOK_OK;
 }
 
@@ -452,24 +580,37 @@ tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W
   if (!valid_drop(drop)) return fail(TOK_EINVAL, "bad drop descriptor");
   Dims d;
   if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
-  const Plan p = make_plan(d, m->prec);
-  if (ws_bytes < p.total) return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
+  Plan p;
+  if (!choose_chunk(d, m->prec, ws_bytes, &p))
+    return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
   Ws w{static_cast<char*>(ws), p};
-  // conv_in: u8 -> level 0 (+ stats for enc.rb1.gn_a)
-  TOK_TRY(conv(m, L_CONV_IN, CM_S1, x, IN_U8, N, T, H, W, 3, w.l0a(), OUT_ACT, T, H, W, nullptr, nullptr, nullptr,
-               w.stats(), s));
-  TOK_TRY(gn_final(m, N_E_RB1_A, w, N * T, H, W, s));
-  TOK_TRY(resblocks(m, L_E_RB1_A, N_E_RB1_A, w, d, false, s));
-  TOK_TRY(conv(m, L_DOWN1, CM_S2, w.l0a(), IN_ACT, N, T, H, W, 64, w.l1(), OUT_ACT, d.T1, d.H1, d.W1, nullptr,
-               nullptr, nullptr, nullptr, s));
-  TOK_TRY(conv(m, L_DOWN2, CM_S2, w.l1(), IN_ACT, N, d.T1, d.H1, d.W1, 128, w.l2(), OUT_ACT, d.T2, d.H2, d.W2,
-               nullptr, nullptr, nullptr, nullptr, s));
   const FsqConst fc = make_fsq_const();
   const DropArgs da = make_drop(drop);
   const int CH = m->prec == P_BF16 ? 32 : 16;
-  Timed tm(m, L_PROJ, s);
-  TOK_HIP(launch_proj_fsq(w.l2(), m->prec, N, d.T2, d.H2, d.W2, 128 / CH, m->w1x1[L_PROJ], m->bias[L_PROJ], fc, da,
-                          z, codes, idx, keep, s));
+  const size_t es = m->prec == P_BF16 ? 2 : 4;
+  const size_t f0b = (size_t)H * W * 64 * es, f1b = (size_t)d.H1 * d.W1 * 128 * es;
+  const Win pix{T, 0, 0, T};  // the uint8 clip: every frame resident
+  const bool chunked = p.CL < d.T2;
+  for (int L0 = 0; L0 < d.T2; L0 += p.CL) {
+    const int L1 = std::min(L0 + p.CL, d.T2);
+    const ChunkWins c = chunk_windows(p, L0, L1);
+    TOK_TRY(conv(m, L_CONV_IN, CM_S1, x, IN_U8, N, pix, H, W, 3, w.l0a(), OUT_ACT, c.l0, H, W, nullptr, w.stats(), s));
+    TOK_TRY(resblocks(m, L_E_RB1_A, N_E_RB1_A, w, d, c.l0, false, chunked, L0, s));
+    TOK_TRY(conv(m, L_DOWN1, CM_S2, w.l0a(), IN_ACT, N, c.l0, H, W, 64, w.l1(), OUT_ACT, c.l1, d.H1, d.W1, nullptr,
+                 nullptr, s));
+    const Win l2e{p.Tb2, L0, 0, L1 - L0};  // encoder latent activations: no cache needed
+    TOK_TRY(conv(m, L_DOWN2, CM_S2, w.l1(), IN_ACT, N, c.l1, d.H1, d.W1, 128, w.l2(), OUT_ACT, l2e, d.H2, d.W2,
+                 nullptr, nullptr, s));
+    {
+      Timed tm(m, L_PROJ, s);
+      TOK_HIP(launch_proj_fsq(w.l2(), m->prec, N, p.Tb2, 0, L1 - L0, d.T2, L0, d.H2, d.W2, 128 / CH,
+                              m->w1x1[L_PROJ], m->bias[L_PROJ], fc, da, z, codes, idx, keep, s));
+    }
+    if (L1 < d.T2) {
+      TOK_TRY(shift_cache(w.l0a(), c.l0, N, f0b, kCache0, s));
+      TOK_TRY(shift_cache(w.l1(), c.l1, N, f1b, kCache1, s));
+    }
+  }
   return TOK_OK;
 }
 
@@ -495,23 +636,37 @@ tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, i
   if (T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
   Dims d;
   if (!make_dims(N, 4 * (T2 - 1) + 1, 4 * H2, 4 * W2, &d)) return fail(TOK_ESHAPE, "bad latent shape");
-  const Plan p = make_plan(d, m->prec);
-  if (ws_bytes < p.total) return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
+  Plan p;
+  if (!choose_chunk(d, m->prec, ws_bytes, &p))
+    return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
   Ws w{static_cast<char*>(ws), p};
   const int CH = m->prec == P_BF16 ? 32 : 16;
-  {
-    Timed tm(m, L_PROJ_IN, s);
-    TOK_HIP(launch_proj_in(codes, (size_t)N * T2 * H2 * W2, m->w1x1[L_PROJ_IN], m->bias[L_PROJ_IN], m->prec,
-                           w.l2(), 128 / CH, H2 * W2, s));
+  const size_t es = m->prec == P_BF16 ? 2 : 4;
+  const size_t f0b = (size_t)d.H * d.W * 64 * es, f1b = (size_t)d.H1 * d.W1 * 128 * es;
+  const size_t f2b = (size_t)d.H2 * d.W2 * 128 * es;
+  const bool chunked = p.CL < d.T2;
+  for (int L0 = 0; L0 < d.T2; L0 += p.CL) {
+    const int L1 = std::min(L0 + p.CL, d.T2);
+    const ChunkWins c = chunk_windows(p, L0, L1);
+    {
+      Timed tm(m, L_PROJ_IN, s);
+      TOK_HIP(launch_proj_in(codes, N, d.T2, L0, L1 - L0, H2 * W2, m->w1x1[L_PROJ_IN], m->bias[L_PROJ_IN], m->prec,
+                             w.l2(), 128 / CH, p.Tb2, c.l2.first, s));
+    }
+    TOK_TRY(conv(m, L_UP2, CM_UPF, w.l2(), IN_ACT, N, c.l2, d.H2, d.W2, 128, w.l1(), OUT_ACT, c.l1, d.H1, d.W1,
+                 nullptr, nullptr, s));
+    TOK_TRY(conv(m, L_UP1, CM_UPF, w.l1(), IN_ACT, N, c.l1, d.H1, d.W1, 128, w.l0a(), OUT_ACT, c.l0, d.H, d.W,
+                 nullptr, w.stats(), s));
+    TOK_TRY(resblocks(m, L_D_RB1_A, N_D_RB1_A, w, d, c.l0, false, chunked, L0, s));
+    const Win ow{d.T, 0, c.l0.g0 + c.l0.first, c.l0.count};
+    TOK_TRY(conv(m, L_CONV_OUT, CM_S1, w.l0a(), IN_ACT, N, c.l0, d.H, d.W, 64, xhat, OUT_RGB32, ow, d.H, d.W, nullptr,
+                 nullptr, s));
+    if (L1 < d.T2) {
+      TOK_TRY(shift_cache(w.l2(), c.l2, N, f2b, kCache2, s));
+      TOK_TRY(shift_cache(w.l1(), c.l1, N, f1b, kCache1, s));
+      TOK_TRY(shift_cache(w.l0a(), c.l0, N, f0b, kCache0, s));
+    }
   }
-  TOK_TRY(conv(m, L_UP2, CM_UP, w.l2(), IN_ACT, N, d.T2, d.H2, d.W2, 128, w.l1(), OUT_ACT, d.T1, d.H1, d.W1,
-               nullptr, nullptr, nullptr, nullptr, s));
-  TOK_TRY(conv(m, L_UP1, CM_UP, w.l1(), IN_ACT, N, d.T1, d.H1, d.W1, 128, w.l0a(), OUT_ACT, d.T, d.H, d.W,
-               nullptr, nullptr, nullptr, w.stats(), s));
-  TOK_TRY(gn_final(m, N_D_RB1_A, w, N * d.T, d.H, d.W, s));
-  TOK_TRY(resblocks(m, L_D_RB1_A, N_D_RB1_A, w, d, false, s));
-  TOK_TRY(conv(m, L_CONV_OUT, CM_S1, w.l0a(), IN_ACT, N, d.T, d.H, d.W, 64, xhat, OUT_RGB32, d.T, d.H, d.W, nullptr,
-               nullptr, nullptr, nullptr, s));
   return TOK_OK;
 }
 

@@ -78,7 +78,10 @@ class TokModel:
         except Exception:
             pass
 
-    def workspace_size(self, N, T, H, W, what=L.TOK_WS_ROUNDTRIP) -> int:
+    def workspace_size(self, N, T, H, W, what=L.TOK_WS_ROUNDTRIP, stream=False) -> int:
+        """Workspace bytes; stream=True sizes it for causal temporal chunking."""
+        if stream:
+            what |= L.TOK_WS_STREAM
         n = C.c_size_t()
         L.check("tok_workspace_size", self.lib.tok_workspace_size(self.handle, N, T, H, W, what, C.byref(n)))
         return int(n.value)
@@ -123,7 +126,7 @@ class TokModel:
         return xh
 
 
-KERNEL_IDS = 17
+KERNEL_IDS = 18
 
 
 class Profile:
@@ -171,3 +174,77 @@ def drop(codes: torch.Tensor | None, d: Drop, shape=None, keep=True):
     desc = d.desc()
     L.check("tok_drop", L.lib().tok_drop(C.byref(desc), _ptr(codes), _ptr(kp), N, T2, H2, W2, _stream(dev)))
     return kp
+
+
+class TokServer:
+    """tok_server: streaming request loop with continuous batching under an HBM budget."""
+
+    def __init__(self, model: TokModel, budget_bytes: int, slots: int = 4, max_batch: int = 4):
+        self.model = model
+        self.lib = model.lib
+        h = C.c_void_p()
+        L.check("tok_server_create", self.lib.tok_server_create(model.handle, int(budget_bytes), slots, max_batch,
+                                                                 C.byref(h)))
+        self.handle = h
+        self._pixels = {}
+
+    def request_bytes(self, T, H, W) -> int:
+        n = C.c_size_t()
+        L.check("tok_server_request_bytes", self.lib.tok_server_request_bytes(self.model.handle, T, H, W,
+                                                                               C.byref(n)))
+        return int(n.value)
+
+    def submit(self, pixels: torch.Tensor, drop: Drop | None = None) -> int:
+        """pixels: host uint8 (T,H,W,3), ideally pinned; kept alive until the request is released."""
+        assert pixels.dtype == torch.uint8 and not pixels.is_cuda and pixels.is_contiguous()
+        T, H, W, _ = pixels.shape
+        d = (drop or Drop()).desc()
+        req = L.Request(T, H, W, pixels.data_ptr(), d)
+        t = C.c_uint64()
+        L.check("tok_server_submit", self.lib.tok_server_submit(self.handle, C.byref(req), C.byref(t)))
+        self._pixels[t.value] = pixels
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """Result metadata (dict) once done, or None on time-out."""
+        r = L.Result()
+        rc = self.lib.tok_server_wait(self.handle, ticket, timeout_ms, C.byref(r))
+        if rc > 0:
+            return None
+        L.check("tok_server_wait", rc)
+        return dict(ticket=r.ticket, status=r.status, latent=(r.T2, r.H2, r.W2), queue_ms=r.queue_ms,
+                    run_ms=r.run_ms, total_ms=r.total_ms, batch_size=r.batch_size)
+
+    def fetch(self, ticket: int, T: int, H: int, W: int):
+        """Copy a finished request's results into new device tensors."""
+        T2, H2, W2 = latent_shape(T, H, W)
+        dev = torch.device("cuda:%d" % self.model.device)
+        codes = torch.empty((T2, H2, W2, 6), dtype=torch.float32, device=dev)
+        idx = torch.empty((T2, H2, W2), dtype=torch.int32, device=dev)
+        keep = torch.empty((T2, H2, W2), dtype=torch.uint8, device=dev)
+        xhat = torch.empty((T, H, W, 3), dtype=torch.float32, device=dev)
+        L.check("tok_server_copy_result", self.lib.tok_server_copy_result(
+            self.handle, ticket, _ptr(codes), _ptr(idx), _ptr(keep), _ptr(xhat), _stream(dev)))
+        return dict(codes=codes, idx=idx, keep=keep, xhat=xhat)
+
+    def release(self, ticket: int):
+        L.check("tok_server_release", self.lib.tok_server_release(self.handle, ticket))
+        self._pixels.pop(ticket, None)
+
+    def stats(self):
+        q, r, f = C.c_int(), C.c_int(), C.c_int()
+        u, p = C.c_size_t(), C.c_size_t()
+        L.check("tok_server_stats", self.lib.tok_server_stats(self.handle, C.byref(q), C.byref(r), C.byref(f),
+                                                              C.byref(u), C.byref(p)))
+        return dict(queued=q.value, running=r.value, finished=f.value, bytes_in_use=u.value, bytes_peak=p.value)
+
+    def close(self):
+        if self.handle:
+            self.lib.tok_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
