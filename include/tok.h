@@ -170,9 +170,10 @@ const char* tok_kernel_name(int k);
  * (Sec. 7 codec wrapper: weights stay resident; Sec. 6: the sender encodes and
  * the receiver decodes continuously).  A tok_server owns one device arena of
  * `budget_bytes` (allocated once, at create) and `slots` HIP streams.  A
- * scheduler thread admits queued clips, oldest first, whenever a stream slot
- * is free and the clip's memory fits in the arena; queued clips of identical
- * shape (up to `max_batch`) are admitted together as one batched launch.
+ * scheduler thread admits queued clips strictly oldest first, whenever a
+ * stream slot is free and the clip's memory fits in the arena; the run of
+ * consecutive queued clips of identical shape at the head of the queue (up to
+ * `max_batch`) is admitted together as one batched launch.
  * Admitted work runs asynchronously and overlaps with work on the other
  * slots; memory returns to the arena when the client releases a result.
  * A clip's result does not depend on what it was batched with.

@@ -208,10 +208,15 @@ struct tok_server {
     for (size_t i = 0; i < slot_batch.size(); ++i)
       if (!slot_batch[i]) { k = (int)i; break; }
     if (k < 0 || queue.empty()) return false;
+    // Admission is strictly first-in first-out: a batch is the head plus the
+    // run of consecutive queued clips of the same shape.  A queued clip is then
+    // never older than an admitted one, so a client that waits for results in
+    // submission order and holds the results of later clips meanwhile can never
+    // starve the clip it waits for of arena memory.
     Request* head = queue.front();
     std::vector<Request*> cand{head};
-    for (size_t i = 1; i < queue.size() && (int)cand.size() < max_batch; ++i)
-      if (queue[i]->shape == head->shape) cand.push_back(queue[i]);
+    for (size_t i = 1; i < queue.size() && (int)cand.size() < max_batch && queue[i]->shape == head->shape; ++i)
+      cand.push_back(queue[i]);
     // largest batch that fits the arena now
     while (!cand.empty()) {
       const int n = (int)cand.size();

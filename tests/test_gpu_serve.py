@@ -94,13 +94,16 @@ def test_oversized_request_refused_and_loop_keeps_serving(tk, model):
 
 def test_budget_bounds_concurrency(tk, model):
     """With room for one clip at a time the clips still all finish, serially."""
-    shape = (5, 48, 64)
-    need = model.workspace_size(1, *shape)
-    sv = tk.TokServer(model, int(need * 1.6) + (8 << 20), slots=4, max_batch=4)
+    shape = (9, 48, 64)
+    probe = tk.TokServer(model, 1 << 30, slots=1, max_batch=1)
+    need = probe.request_bytes(*shape)  # streaming workspace + clip buffers
+    probe.close()
+    budget = int(need * 1.5)
+    sv = tk.TokServer(model, budget, slots=4, max_batch=4)
     ts = [sv.submit(_clip(i, *shape)) for i in range(5)]
     for t in ts:
         r = sv.wait(t, timeout_ms=60000)
         assert r is not None and r["status"] == 0 and r["batch_size"] == 1
         sv.release(t)
-    assert sv.stats()["bytes_peak"] <= int(need * 1.6) + (8 << 20)
+    assert sv.stats()["bytes_peak"] <= budget
     sv.close()
