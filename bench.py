@@ -21,6 +21,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tokenizer encode+decode frames/s at 720p, BF16 vs FP32, ≤0.5 dB PSNR vs oracle"
 BF16_PEAK_TFLOPS = 2500.0
+# Mean HBM bytes per launch of the level-0 residual-block conv at 4 x 17 x
+# 1280x720 BF16, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled
+# by the same counters on a 1 GiB device copy; see profiles/.  Valid for that
+# workload and the conv kernel as measured; other shapes report null.
+RB_CONV_HBM_BYTES_720P = 27.34e9
 F32_PEAK_TFLOPS = 157.3
 # FLOPs per output position of each conv (2 * 27 * Cin * Cout, 1x1x1: 2 * Cin * Cout) and the level it runs at.
 CONV_FLOPS = {
@@ -153,9 +158,15 @@ def main():
     rb_avg_ms = rb_ms / rb_n
     rb_flops = CONV_FLOPS["enc.rb1.a"][0] * pos[0]
     achieved = rb_flops / (rb_avg_ms / 1e3) / 1e12
+    # in + out per launch, plus the residual read on the 4 second convs of the 8
+    rb_io_bytes = pos[0] * 64 * 2 * 2 + pos[0] * 64 * 2 // 2
+    rb_traffic = RB_CONV_HBM_BYTES_720P if (N, T, H, W) == (4, 17, 720, 1280) else None
     roofline = dict(kernel="level-0 residual-block conv 64->64 (bf16 MFMA, GN+SiLU prologue)", bound="mfma",
                     achieved=round(achieved, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / BF16_PEAK_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / BF16_PEAK_TFLOPS, 4), traffic=rb_traffic,
+                    traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
+                                 "calibrated on a 1 GiB device copy)",
+                    algorithmic_bytes=rb_io_bytes,
                     avg_launch_ms=round(rb_avg_ms, 4), flops_per_launch=rb_flops,
                     share_of_step=round(rb_ms / args.steps / ms_b, 3))
     total_flops = algorithmic_flops(N, T, H, W)
