@@ -59,6 +59,61 @@ def blas_threads():
     return os.cpu_count() or 1
 
 
+def train_flops(N, T, H, W):
+    """Algorithmic FLOPs of one training step: every conv's forward, weight
+    gradient and input gradient (none for the first layer's input), plus the
+    recomputed first conv of each of the 4 residual blocks."""
+    pos = level_positions(N, T, H, W)
+    f = 0
+    for name, (fl, lv) in CONV_FLOPS.items():
+        f += fl * pos[lv] * (2 if name == "enc.conv_in" else 3)
+    f += 4 * CONV_FLOPS["enc.rb1.a"][0] * pos[0]
+    return f
+
+
+def train_leg(tok, synth, wflat, dev, args):
+    import torch
+    N, T, H, W = (int(v) for v in args.train_shape.split("x"))
+    x = torch.from_numpy(synth.make_batch(list(range(N)), T, H, W)).to(dev)
+    out = dict(workload="training step (loss forward + hand-written backward with per-block recompute), "
+                        "%d clips x %d frames x %dx%d" % (N, T, W, H),
+               batch=N, frames=T, height=H, width=W, steps=args.train_steps,
+               algorithmic_tflops_per_step=round(train_flops(N, T, H, W) / 1e12, 3))
+    for prec in ("bf16", "f32"):
+        m = tok.TokModel(wflat, prec)
+        ws = torch.empty(m.train_workspace_size(N, T, H, W), dtype=torch.uint8, device=dev)
+        dw = torch.empty(tok.weight_count(), dtype=torch.float32, device=dev)
+
+        def step():
+            f = m.train_forward(x, ws=ws)
+            m.backward(x, ws, dweights=dw)
+            return f["loss"]
+        loss = step()
+        torch.cuda.synchronize()
+        print("bench: train %s warm-up done" % prec, file=sys.stderr, flush=True)
+        prof = tok.Profile(m)
+        prof.__enter__()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.train_steps):
+            loss = step()
+        e1.record()
+        torch.cuda.synchronize()
+        prof.__exit__(None, None, None)
+        ms = e0.elapsed_time(e1) / args.train_steps
+        kern = {k: round(v / args.train_steps, 3) for k, v in prof.ms.items() if prof.count[k]}
+        out[prec] = dict(ms_per_step=round(ms, 2), frames_per_s=round(N * T / (ms / 1e3), 2),
+                         tflops=round(train_flops(N, T, H, W) / (ms / 1e3) / 1e12, 2),
+                         loss=float(loss[0]), ms_per_step_by_kernel=kern,
+                         workspace_gb=round(ws.numel() / 1e9, 2))
+        print("bench: train %s %.2f ms/step" % (prec, ms), file=sys.stderr, flush=True)
+        del ws, dw
+        m.close()
+        torch.cuda.empty_cache()
+    out["bf16_speedup_vs_f32"] = round(out["f32"]["ms_per_step"] / out["bf16"]["ms_per_step"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +126,9 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--cpu-crop", type=str, default="180x320", help="HxW crop of clip 0 frame 0 for the oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=3,
+                    help="timed training steps (forward + backward) per precision; 0 skips the training leg")
+    ap.add_argument("--train-shape", type=str, default="8x17x256x256", help="NxTxHxW of the training batch")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -184,6 +242,11 @@ def main():
         print("bench: f32 %.2f ms/step" % ms_f, file=sys.stderr, flush=True)
         mf.close()
 
+    # ---- training step: forward + hand-written backward, BF16 vs FP32 -------
+    train = None
+    if args.train_steps > 0:
+        train = train_leg(tok, synth, wflat, dev, args)
+
     # ---- CPU oracle on a bounded sample + PSNR criterion on that sample ----
     cpu = None
     psnr = None
@@ -221,7 +284,7 @@ def main():
                             batch=N, frames=T, height=H, width=W, precision="bf16"),
                 algorithmic_tflops_per_step=round(total_flops / 1e12, 3),
                 achieved_tflops=round(total_flops / (ms_b / 1e3) / 1e12, 2),
-                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, per_kernel=per_kernel)
+                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, train=train, per_kernel=per_kernel)
     print(json.dumps(line), flush=True)
 
 

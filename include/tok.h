@@ -25,7 +25,7 @@
  *  - Every tensor argument is a DEVICE pointer unless marked "host".  The
  *    caller owns every tensor and the workspace; the library owns only the
  *    packed weights inside a tok_model.  No call allocates device memory
- *    except tok_model_create.
+ *    except tok_model_create and tok_server_create.
  *  - Pixel and output tensors are dense NDHWC: x is uint8 (N,T,H,W,3),
  *    x_hat is float32 (N,T,H,W,3).  Latent tensors are dense float32
  *    (N,T2,H2,W2,6); idx is int32 (N,T2,H2,W2); keep is uint8 (N,T2,H2,W2).
@@ -156,12 +156,58 @@ tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H
  * frees the events.  Kernel ids: 0..15 the convolution layers in blob order
  * (conv_in, enc rb1.a, rb1.b, rb2.a, rb2.b, down1, down2, proj, proj_in, up2,
  * up1, dec rb1.a, rb1.b, rb2.a, rb2.b, conv_out; 7 and 8 are the fused
- * projection kernels), 16 GroupNorm finalize; tok_kernel_name(k) names them.
+ * projection kernels), 16 GroupNorm finalize, 17 GroupNorm apply + SiLU,
+ * and for tok_train_forward / tok_backward: 18 adjoint (input-gradient)
+ * convolutions, 19 weight-gradient kernels, 20 GroupNorm+SiLU backward,
+ * 21 other backward kernels; tok_kernel_name(k) names them.
  * Profiling allocates events and is meant for measurement runs; do not
  * profile one model from several host threads at once. */
 tok_status tok_profile_begin(tok_model* model);
 tok_status tok_profile_end(tok_model* model, int n_ids, double* ms, int* count);
 const char* tok_kernel_name(int k);
+
+/* ---------------------------------------------------------------------------
+ * Training step.  The codec is trained end to end and gradients flow through
+ * the whole tokenizer (Sec. 4.1 gradient interface; Appendix, Eq. 5 l1 pixel
+ * term, and Eq. 7 training on token-dropped latents).  Objective of the
+ * stand-in:
+ *   L = mean |x_hat - x| + 0.1 * mean (z~ - sg(c))^2
+ * over the N*T*H*W*3 pixels and the M = N*T2*H2*W2*6 latent values, with
+ * z~ = b / floor(L/2) the unrounded normalised code, c its FSQ code, the
+ * decoder reading keep * c, the straight-through rule dc/dz~ = 1 and
+ * sign(0) = 0 as the l1 subgradient.  tok_train_forward stores a tape of
+ * block-boundary activations in the workspace; tok_backward recomputes each
+ * residual block's interior from it (per-block checkpointing) and writes the
+ * gradient of every parameter.
+ * -------------------------------------------------------------------------*/
+
+/* Replace the model's parameters by the device float32 blob `weights`
+ * (canonical order, tok_weight_count() floats) and repack its kernels, on
+ * `stream`.  Must not overlap with other work that uses the model. */
+tok_status tok_model_set_weights(tok_model* model, const float* weights, hipStream_t stream);
+
+/* Bytes of workspace for tok_train_forward + tok_backward on N clips of
+ * T x H x W (whole clips; the tape lives in it between the two calls). */
+tok_status tok_train_workspace_size(const tok_model* model, int N, int T, int H, int W, size_t* bytes);
+
+/* Forward pass of the objective.  x: uint8 (N,T,H,W,3).  keep: uint8
+ * (N,T2,H2,W2) token mask (1 = kept) or NULL for all kept.  loss: device
+ * float[3] receiving {L, l1 term, commitment mean}.  xhat, z (float32) and
+ * idx (int32) are optional copies of the reconstruction, pre-quantisation
+ * latent and code indices.  The tape stays valid in ws until the next call
+ * that uses ws. */
+tok_status tok_train_forward(tok_model* model, const uint8_t* x, int N, int T, int H, int W,
+                             const uint8_t* keep, float* loss, float* xhat, float* z, int32_t* idx,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward pass of the last tok_train_forward on the same x, shape and ws.
+ * gloss: device float scalar dOut/dL (NULL = 1).  dweights: device float32
+ * (tok_weight_count()) receiving dL/dparameters in canonical blob order
+ * (every entry is written).  dx: optional float32 (N,T,H,W,3) receiving
+ * dL/dx for the normalised input x/127.5 - 1. */
+tok_status tok_backward(tok_model* model, const uint8_t* x, int N, int T, int H, int W,
+                        const float* gloss, float* dweights, float* dx, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Streaming request loop (continuous batching under an HBM budget).

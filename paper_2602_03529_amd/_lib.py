@@ -67,6 +67,14 @@ def lib():
     L.tok_drop.argtypes = [C.POINTER(DropDesc), vp, vp, i32, i32, i32, i32, vp]
     L.tok_decode.restype = i32
     L.tok_decode.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.tok_model_set_weights.restype = i32
+    L.tok_model_set_weights.argtypes = [vp, vp, vp]
+    L.tok_train_workspace_size.restype = i32
+    L.tok_train_workspace_size.argtypes = [vp, i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_train_forward.restype = i32
+    L.tok_train_forward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.tok_backward.restype = i32
+    L.tok_backward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp]
     L.tok_profile_begin.restype = i32
     L.tok_profile_begin.argtypes = [vp]
     L.tok_profile_end.restype = i32

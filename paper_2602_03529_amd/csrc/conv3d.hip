@@ -24,6 +24,8 @@
 // then every wave runs 9 taps x (its position blocks x channel blocks) MFMAs.
 // 16-byte quads inside a 64-byte LDS row are XOR-swizzled by the row index so
 // that the 16 lanes reading 16 consecutive rows hit distinct banks.
+#include <utility>
+
 #include "tok_internal.h"
 #include "tok_device.h"
 
@@ -42,6 +44,7 @@ __host__ __device__ __forceinline__ int swz(int row) { return (row >> TOK_SWZ_SH
 template <int PREC> struct Op;
 template <> struct Op<P_F32> { static constexpr int CH = 16; static constexpr int QE = 4; };
 template <> struct Op<P_BF16> { static constexpr int CH = 32; static constexpr int QE = 8; };
+template <> struct Op<P_FP8> { static constexpr int CH = 64; static constexpr int QE = 16; };
 
 // Per mode: output tile TH x TW, halo HH x HW (rows x positions), position
 // blocks per wave MB, weight tap-matrices per stage WT, temporal stages KTS.
@@ -58,6 +61,8 @@ template <> struct Geo<CM_UP> {
   static constexpr int WR = 2, TW = 64, TH = 8, HH = TH / 2 + 2, HW = TW / 2 + 2;
   static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
+template <> struct Geo<CM_S1T> : Geo<CM_S1> {};
+
 // Polyphase upsample conv: wave w owns output phase (h & 1, w & 1) = (w >> 1, w & 1)
 // of the tile, i.e. 4 source rows x 32 source columns = 8 blocks; a stage holds
 // the 2 x 2 folded taps of all 4 phases.
@@ -84,7 +89,7 @@ __device__ __forceinline__ void out_local(int wave, int m, int l16, int* i, int*
 template <int MODE>
 __device__ __forceinline__ int act_row(int i, int j, int kh, int kw) {
   using G = Geo<MODE>;
-  if constexpr (MODE == CM_S1) {
+  if constexpr (MODE == CM_S1 || MODE == CM_S1T) {
     return (i + kh) * G::HW + (j + kw);
   } else if constexpr (MODE == CM_S2) {
     const int c = 2 * j + kw;
@@ -100,7 +105,7 @@ __device__ __forceinline__ void halo_src(int p, int h0, int w0, int* hs, int* ws
   using G = Geo<MODE>;
   const int r = p / G::HW;
   const int pc = p - r * G::HW;
-  if constexpr (MODE == CM_S1) {
+  if constexpr (MODE == CM_S1 || MODE == CM_S1T) {
     *hs = h0 - 1 + r;
     *ws = w0 - 1 + pc;
   } else if constexpr (MODE == CM_S2) {
@@ -132,6 +137,20 @@ __device__ __forceinline__ void mfma_quad(f32x4& acc, const uint4& wq, const uin
   }
 }
 
+// fp8 operand of one lane for the K = 128 MFMA: the 32 bytes (channels
+// 32 hb .. 32 hb + 31 of a 64-channel row) in logical quads 2 hb and 2 hb + 1.
+__device__ __forceinline__ i32x8 ld_fp8_half(const uint4* base, int row, int hb) {
+  const uint4 q0 = base[row * 4 + ((2 * hb) ^ swz(row))];
+  const uint4 q1 = base[row * 4 + ((2 * hb + 1) ^ swz(row))];
+  return i32x8{(int)q0.x, (int)q0.y, (int)q0.z, (int)q0.w, (int)q1.x, (int)q1.y, (int)q1.z, (int)q1.w};
+}
+
+// D += A x B on e4m3 operands with K = 128: A (weights) unscaled, B
+// (activations) scaled per lane by the E8M0 byte sb.
+__device__ __forceinline__ void mfma_fp8(f32x4& acc, const i32x8& w, const i32x8& x, int sb) {
+  acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, sb);
+}
+
 // Map a linear block index to a virtual tile index so that the blocks one XCD
 // receives (hardware dispatches block b to XCD b % 8) are contiguous tiles.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -144,6 +163,9 @@ template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, boo
 __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch a) {
   using G = Geo<MODE>;
   using O = Op<PREC>;
+  constexpr bool F8 = PREC == P_FP8;
+  constexpr int OPREC = F8 ? P_BF16 : PREC;  // precision of OUT_ACT stores and of the residual
+  using OO = Op<OPREC>;
   constexpr int NT = NB * 16;           // output channels per workgroup
   constexpr int HALO = G::HH * G::HW;   // halo rows (positions)
   constexpr int MB = G::MB;             // position blocks per wave
@@ -152,9 +174,13 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   constexpr int NBUF = DB ? 2 : 1;      // LDS buffers (double buffering: 1 workgroup per CU)
   static_assert(WQ % 64 == 0, "weight stage must be whole waves");
   static_assert(!DB || IN_KIND == IN_ACT, "double buffering needs asynchronous staging");
+  static_assert(!F8 || (IN_KIND == IN_ACT && !DB), "fp8: activations in, single buffer");
+  static_assert(OUT_KIND != OUT_FP8 || (F8 && !STATS && NB == 4), "fp8 output: fp8 kernels, no statistics");
+  constexpr int SCN = F8 ? HALO : 1;      // fp8: two E8M0 bytes per halo row
 
   __shared__ uint4 lds_a[NBUF][HQ];
   __shared__ uint4 lds_w[NBUF][WQ];
+  __shared__ uint16_t lds_sc[SCN];
   __shared__ float red[kWaves][32];
   __shared__ float gmean[32];
 
@@ -183,7 +209,10 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   const size_t plane_in = (size_t)a.Hi * a.Wi;
   // Folded weights come in two sets, one per output-frame parity.
   const int tg = a.go0 + to;  // global output frame
-  const size_t wset = MODE == CM_UPF ? (size_t)ct * 2 + (tg & 1) : (size_t)ct;
+  // Folded weight sets: per output-frame parity (CM_UPF); frame 0 vs later frames (CM_S1T).
+  size_t wset = ct;
+  if constexpr (MODE == CM_UPF) wset = (size_t)ct * 2 + (tg & 1);
+  if constexpr (MODE == CM_S1T) wset = (size_t)ct * 2 + (tg == 0 ? 1 : 0);
   const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + wset * G::KTS * a.in_chunks * WQ;
   const int nstages = G::KTS * a.in_chunks;  // stage = (temporal tap, input chunk)
 
@@ -192,6 +221,7 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   auto src_frame = [&](int kt) {
     int g;
     if constexpr (MODE == CM_S1) g = max(tg + kt - 2, 0);
+    else if constexpr (MODE == CM_S1T) g = tg + kt;  // gradient frames t, t+1, t+2 (past the end: none)
     else if constexpr (MODE == CM_S2) g = max(2 * tg + kt - 2, 0);
     else if constexpr (MODE == CM_UP) g = (max(tg + kt - 2, 0) + 1) >> 1;
     else {
@@ -218,6 +248,19 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
       if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) hoff[k] = (hs * a.Wi + ws) * 4 + q;
     }
   }
+  // fp8: in-frame position of halo rows tid, tid + 256, ... (scale staging), -1 outside
+  constexpr int NSR = F8 ? (HALO + kThreads - 1) / kThreads : 1;
+  int soff[NSR];
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) {
+    soff[k] = -1;
+    const int p = tid + k * kThreads;
+    if (F8 && p < HALO) {
+      int hs, ws;
+      halo_src<MODE>(p, h0, w0, &hs, &ws);
+      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) soff[k] = hs * a.Wi + ws;
+    }
+  }
 
   // Issue the global->LDS transfers of stage st into buffer buf: the 9 taps of
   // packed weights and the spatial halo, both as direct-to-LDS loads (lane l
@@ -238,6 +281,16 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
       if (e < HQ) {
         if (hoff[k] >= 0) lds_dma16(src + hoff[k], &lds_a[buf][base]);
         else lds_a[buf][e] = make_uint4(0, 0, 0, 0);
+      }
+    }
+    if constexpr (F8) {
+      // scale bytes of the halo rows (rows outside the frame: zeros with scale 2^0)
+      const uint16_t* ssrc = reinterpret_cast<const uint16_t*>(a.in_scale) +
+                             (((size_t)n * a.Ti + src_frame(kt)) * a.in_chunks + ck) * plane_in;
+#pragma unroll
+      for (int k = 0; k < NSR; ++k) {
+        const int p = tid + k * kThreads;
+        if (p < HALO) lds_sc[p] = soff[k] >= 0 ? ssrc[soff[k]] : (uint16_t)0x7F7F;
       }
     }
   };
@@ -288,6 +341,56 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   // The 9 spatial taps of one stage: every wave multiplies its MB position
   // blocks by the NB output-channel blocks.
   auto compute = [&](int buf) {
+    if constexpr (F8) {
+      // K = 128 per MFMA = two taps x 64 channels: lane group g4 takes tap
+      // 2 pr + (g4 >> 1), channels 32 (g4 & 1) .. +31, with its scale byte.
+      const int hb = g4 & 1;
+      if constexpr (MODE == CM_UPF) {
+        const int ph = wave >> 1, pw = wave & 1;
+#pragma unroll 1
+        for (int pr = 0; pr < 2; ++pr) {
+          const int tap = 2 * pr + (g4 >> 1);
+          const int dh = tap >> 1, dw = tap & 1;
+          i32x8 wq[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) wq[b] = ld_fp8_half(lds_w[buf], (wave * 4 + tap) * NT + b * 16 + l16, hb);
+#pragma unroll
+          for (int m = 0; m < MB; ++m) {
+            const int row = ((m >> 1) + dh + ph) * G::HW + ((m & 1) * 16 + l16 + dw + pw);
+            const i32x8 aq = ld_fp8_half(lds_a[buf], row, hb);
+            const int sb = (lds_sc[row] >> (8 * hb)) & 255;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) mfma_fp8(acc[m][b], wq[b], aq, sb);
+          }
+        }
+      } else {
+        constexpr int BPR = G::TW / 16;
+#pragma unroll 1
+        for (int pr = 0; pr < 5; ++pr) {
+          const int tp = 2 * pr + (g4 >> 1);
+          const bool tv = tp < 9;  // the 10th "tap" has zero weights
+          const int tap = tv ? tp : 8;
+          const int kh = tap / 3, kw = tap % 3;
+          i32x8 wq[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            wq[b] = ld_fp8_half(lds_w[buf], tap * NT + b * 16 + l16, hb);
+            if (!tv) wq[b] = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+          }
+#pragma unroll
+          for (int m = 0; m < MB; ++m) {
+            const int i = wave * G::WR + m / BPR;
+            const int j = (m % BPR) * 16 + l16;
+            const int row = act_row<MODE>(i, j, kh, kw);
+            const i32x8 aq = ld_fp8_half(lds_a[buf], row, hb);
+            const int sb = (lds_sc[row] >> (8 * hb)) & 255;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) mfma_fp8(acc[m][b], wq[b], aq, sb);
+          }
+        }
+      }
+      return;
+    }
     if constexpr (MODE == CM_UPF) {
       const int ph = wave >> 1, pw = wave & 1;
 #pragma unroll
@@ -346,6 +449,9 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
     }
   } else {
     for (int st = 0; st < nstages; ++st) {
+      if constexpr (MODE == CM_S1T) {
+        if (src_frame(st / a.in_chunks) >= a.Ti) continue;  // beyond the last gradient frame (uniform per block)
+      }
       __syncthreads();
       if constexpr (IN_KIND == IN_ACT) issue_async(st, 0);
       else stage_u8(st);
@@ -361,6 +467,61 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
 #pragma unroll
   for (int b = 0; b < NB; ++b) s_lo[b] = s_hi[b] = 0.f;
 
+  if constexpr (OUT_KIND == OUT_FP8) {
+    // MX-FP8 output: per position, one E8M0 scale per 32 channels (b = 0, 1
+    // and b = 2, 3 of this tile), from the block maximum over the 4 lanes
+    // (g4) that hold the position's channels.  Residual (bf16) added first.
+    const int res_chunks = a.Cout / OO::CH;
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      int i, j;
+      out_local<MODE>(wave, m, l16, &i, &j);
+      const int oh = h0 + i, ow = w0 + j;
+      const bool valid = (oh < a.Ho) && (ow < a.Wo);
+      const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
+      const size_t pos = (size_t)oh * a.Wo + ow;
+      float v[NB][4];
+      float am[2] = {0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int c0 = ct * NT + b * 16 + 4 * g4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[b][r] = acc[m][b][r] * a.wscale[c0 + r] + a.bias[c0 + r];
+        if constexpr (RESID) {
+          if (valid) {
+            const uint2 rv = *reinterpret_cast<const uint2*>(
+                reinterpret_cast<const char*>(a.resid) +
+                ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
+            v[b][0] += bf16_lo(rv.x); v[b][1] += bf16_hi(rv.x);
+            v[b][2] += bf16_lo(rv.y); v[b][3] += bf16_hi(rv.y);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) am[b >> 1] = fmaxf(am[b >> 1], fabsf(v[b][r]));
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        am[h] = fmaxf(am[h], __shfl_xor(am[h], 16));
+        am[h] = fmaxf(am[h], __shfl_xor(am[h], 32));
+      }
+      const int e0 = fp8_block_exp(am[0]), e1 = fp8_block_exp(am[1]);
+      const float inv0 = ldexpf(1.0f, -e0), inv1 = ldexpf(1.0f, -e1);
+      if (valid) {
+        char* orow = reinterpret_cast<char*>(a.out) + ((frame * a.out_chunks + ct) * plane_out + pos) * kChunkBytes;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float f = b < 2 ? inv0 : inv1;
+          *reinterpret_cast<uint32_t*>(orow + b * 16 + 4 * g4) =
+              pack_fp8x4(v[b][0] * f, v[b][1] * f, v[b][2] * f, v[b][3] * f);
+        }
+        if (g4 == 0)
+          reinterpret_cast<uint16_t*>(a.out_scale)[(frame * a.out_chunks + ct) * plane_out + pos] =
+              (uint16_t)((e0 + 127) | ((e1 + 127) << 8));
+      }
+    }
+    return;
+  }
+
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     int i, j;
@@ -372,12 +533,16 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
       const int c0 = ct * NT + b * 16 + 4 * g4;
       float v4[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v4[r] = acc[m][b][r] + ((c0 + r) < a.Cout ? a.bias[c0 + r] : 0.f);
+      for (int r = 0; r < 4; ++r) {
+        const bool cv = (c0 + r) < a.Cout;
+        if constexpr (F8) v4[r] = cv ? acc[m][b][r] * a.wscale[c0 + r] + a.bias[c0 + r] : 0.f;
+        else v4[r] = acc[m][b][r] + (cv ? a.bias[c0 + r] : 0.f);
+      }
       if constexpr (OUT_KIND == OUT_ACT) {
-        const int chunk = c0 / O::CH, within = c0 % O::CH;
+        const int chunk = c0 / OO::CH, within = c0 % OO::CH;
         const size_t off = (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
-                           ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * (kChunkBytes / O::CH);
-        if constexpr (PREC == P_BF16) {
+                           ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * (kChunkBytes / OO::CH);
+        if constexpr (OPREC == P_BF16) {
           if (valid) {
             if constexpr (RESID) {
               const uint2 rv = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + off);
@@ -505,6 +670,8 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   if (a.out_kind == OUT_RGB32) {
     if (a.mode == CM_S1 && a.nt == 16 && !res && !st)
       return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false, kDB>(a, s);
+    if (a.mode == CM_S1T && a.nt == 16 && !res && !st)
+      return launch_one<PREC, CM_S1T, 1, IN_ACT, OUT_RGB32, false, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.nt != 64) return hipErrorInvalidValue;
@@ -524,6 +691,10 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
     if (!res && st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
     return hipErrorInvalidValue;
   }
+  if (a.mode == CM_S1T) {
+    if (!res && !st) return launch_one<PREC, CM_S1T, 4, IN_ACT, OUT_ACT, false, false, false>(a, s);
+    return hipErrorInvalidValue;
+  }
   if (a.mode == CM_UPF) {
     if (!res && !st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
     if (!res && st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
@@ -532,13 +703,239 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+
+// ---------------------------------------------------------------------------
+// Weight gradient.  Block = 256 threads (4 waves); block b handles temporal tap
+// kt, a 32-channel slice of the input channels, a 64-channel slice of the
+// output channels and a contiguous share of the (clip, frame, tile) items.
+// Per item it stages the output-gradient tile (256 positions x 64 channels)
+// and the input halo (32 channels) in LDS, then runs fp32 16x16x4 MFMAs with
+// K = output positions: wave w accumulates output channels 16w..16w+15 x the
+// 32 input channels x the 9 spatial taps (18 accumulator blocks).
+// ---------------------------------------------------------------------------
+template <int VIEW> struct WGeo;
+template <> struct WGeo<CM_S1> { static constexpr int TH = 4, TW = 64, HH = TH + 2, HW = TW + 2; };
+template <> struct WGeo<CM_S2> { static constexpr int TH = 4, TW = 32, HH = 2 * TH + 1, HW = 2 * TW + 1; };
+template <> struct WGeo<CM_UP> { static constexpr int TH = 4, TW = 64, HH = TH / 2 + 2, HW = TW / 2 + 2; };
+
+template <int VIEW>
+__device__ __forceinline__ int wg_row(int r, int c, int kh, int kw) {
+  using G = WGeo<VIEW>;
+  if constexpr (VIEW == CM_S1) return (r + kh) * G::HW + c + kw;
+  else if constexpr (VIEW == CM_S2) return (2 * r + kh) * G::HW + 2 * c + kw;
+  else return ((r + kh + 1) >> 1) * G::HW + ((c + kw + 1) >> 1);
+}
+
+template <int PREC>
+__device__ __forceinline__ float ld_elem(const void* base, size_t e) {
+  if constexpr (PREC == P_BF16) return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(base)[e] << 16);
+  else return reinterpret_cast<const float*>(base)[e];
+}
+
+template <int PREC, int VIEW>
+__global__ void __launch_bounds__(256) wgrad_kernel(WgradLaunch a) {
+  using G = WGeo<VIEW>;
+  constexpr int CH = Op<PREC>::CH;
+  constexpr int NPOS = G::TH * G::TW;      // output positions per item
+  constexpr int HALO = G::HH * G::HW;
+  __shared__ float s_dy[NPOS][64 + 1];
+  __shared__ float s_x[HALO][32 + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, k4 = lane >> 4;
+  const int ic_tiles = (a.Cin + 31) / 32, oc_tiles = (a.Cout + 63) / 64;
+  int v = blockIdx.x;
+  const int sp = v % a.splits; v /= a.splits;
+  const int ot = v % oc_tiles; v /= oc_tiles;
+  const int it = v % ic_tiles; v /= ic_tiles;
+  const int kt = v;
+  const int tiles_h = (a.Ho + G::TH - 1) / G::TH, tiles_w = (a.Wo + G::TW - 1) / G::TW;
+  const long long items = (long long)a.N * a.To * tiles_h * tiles_w;
+  const long long i0 = items * sp / a.splits, i1 = items * (sp + 1) / a.splits;
+
+  f32x4 acc[9][2];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // Blocks of temporal tap 0 and the first input-channel slice also sum the
+  // output gradient per channel (the bias gradient), in item order.
+  const bool bias_sum = a.bpartial && kt == 0 && it == 0;
+  float bsum = 0.f;
+
+  const size_t plane_x = (size_t)a.Hi * a.Wi, plane_y = (size_t)a.Ho * a.Wo;
+  for (long long item = i0; item < i1; ++item) {
+    long long u = item;
+    const int tw = (int)(u % tiles_w); u /= tiles_w;
+    const int th = (int)(u % tiles_h); u /= tiles_h;
+    const int to = (int)(u % a.To); u /= a.To;
+    const int n = (int)u;
+    const int h0 = th * G::TH, w0 = tw * G::TW;
+    int ts;
+    if constexpr (VIEW == CM_S1) ts = max(to + kt - 2, 0);
+    else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
+    else ts = (max(to + kt - 2, 0) + 1) >> 1;
+    __syncthreads();
+    // output-gradient tile: 64 channels starting at ot*64
+    for (int e = tid; e < NPOS * 64; e += 256) {
+      const int p = e >> 6, c = e & 63;
+      const int oh = h0 + p / G::TW, ow = w0 + p % G::TW;
+      const int oc = ot * 64 + c;
+      float val = 0.f;
+      if (oh < a.Ho && ow < a.Wo && oc < a.Cout) {
+        const size_t off = (((size_t)n * a.To + to) * a.dy_chunks + oc / CH) * plane_y * CH +
+                           ((size_t)oh * a.Wo + ow) * CH + oc % CH;
+        val = ld_elem<PREC>(a.dy, off);
+      }
+      s_dy[p][c] = val;
+    }
+    // input halo: 32 channels starting at it*32, zero outside the frame
+    for (int e = tid; e < HALO * 32; e += 256) {
+      const int p = e >> 5, c = e & 31;
+      const int r = p / G::HW, q = p % G::HW;
+      int hs, ws;
+      if constexpr (VIEW == CM_S1) { hs = h0 - 1 + r; ws = w0 - 1 + q; }
+      else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + r; ws = 2 * w0 - 1 + q; }
+      else { hs = (h0 >> 1) - 1 + r; ws = (w0 >> 1) - 1 + q; }
+      const int icn = it * 32 + c;
+      float val = 0.f;
+      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && icn < a.Cin) {
+        const size_t off = (((size_t)n * a.Ti + ts) * a.x_chunks + icn / CH) * plane_x * CH +
+                           ((size_t)hs * a.Wi + ws) * CH + icn % CH;
+        val = ld_elem<PREC>(a.x, off);
+      }
+      s_x[p][c] = val;
+    }
+    __syncthreads();
+    if (bias_sum && tid < 64) {
+      for (int p = 0; p < NPOS; ++p) bsum += s_dy[p][tid];
+    }
+    // K = output positions, 4 per MFMA
+    for (int k0 = 0; k0 < NPOS; k0 += 4) {
+      const int p = k0 + k4;
+      const int r = p / G::TW, c = p % G::TW;
+      const float av = s_dy[p][wave * 16 + l16];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int row = wg_row<VIEW>(r, c, t / 3, t % 3);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, s_x[row][b * 16 + l16], acc[t][b], 0, 0, 0);
+      }
+    }
+  }
+  // D block (o, i): lane holds o = 4*k4 + r (r = 0..3), i = l16
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int oc = ot * 64 + wave * 16 + 4 * k4 + r, icn = it * 32 + b * 16 + l16;
+        if (oc < a.Cout && icn < a.Cin)
+          a.partial[((((size_t)sp * 3 + kt) * 9 + t) * a.Cout + oc) * a.Cin + icn] = acc[t][b][r];
+      }
+  if (bias_sum && tid < 64 && ot * 64 + tid < a.Cout) a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = bsum;
+}
+
+// Sums the per-split partials in split order: weights into the canonical
+// [o][i][kt][kh][kw] layout, then (elements past the weights) the bias.
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ partial,
+                                                            const float* __restrict__ bpartial, int splits, int Cout,
+                                                            int Cin, float* __restrict__ dw, float* __restrict__ db) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)Cout * Cin * 27;
+  if (e >= total) {
+    const size_t o = e - total;
+    if (o >= (size_t)Cout || !db) return;
+    float acc = 0.f;
+    for (int s = 0; s < splits; ++s) acc += bpartial[(size_t)s * Cout + o];
+    db[o] = acc;
+    return;
+  }
+  const int tap = (int)(e % 27);
+  const size_t oi = e / 27;
+  const int o = (int)(oi / Cin), i = (int)(oi % Cin);
+  const int kt = tap / 9, t9 = tap % 9;
+  const size_t stride = (size_t)27 * Cout * Cin;
+  const size_t base = (((size_t)kt * 9 + t9) * Cout + o) * Cin + i;
+  float acc = 0.f;
+  for (int s = 0; s < splits; ++s) acc += partial[(size_t)s * stride + base];
+  dw[e] = acc;
+}
+
 }  // namespace
+
+// fp8 decoder convs: MX-FP8 input, outputs bf16 (OUT_ACT), MX-FP8 or RGB.
+hipError_t dispatch_fp8(const ConvLaunch& a, hipStream_t s) {
+  const bool res = a.resid != nullptr, st = a.stats != nullptr;
+  if (a.in_kind != IN_ACT || !a.in_scale || !a.wscale) return hipErrorInvalidValue;
+  if (a.out_kind == OUT_RGB32) {
+    if (a.mode == CM_S1 && a.nt == 16 && !res && !st)
+      return launch_one<P_FP8, CM_S1, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.nt != 64 || a.Cout % 64 != 0) return hipErrorInvalidValue;
+  if (a.out_kind == OUT_FP8) {
+    if (!a.out_scale || st) return hipErrorInvalidValue;
+    if (a.mode == CM_UPF && !res) return launch_one<P_FP8, CM_UPF, 4, IN_ACT, OUT_FP8, false, false>(a, s);
+    if (a.mode == CM_S1 && res) return launch_one<P_FP8, CM_S1, 4, IN_ACT, OUT_FP8, true, false>(a, s);
+    if (a.mode == CM_S1 && !res) return launch_one<P_FP8, CM_S1, 4, IN_ACT, OUT_FP8, false, false>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.out_kind != OUT_ACT) return hipErrorInvalidValue;
+  if (a.mode == CM_UPF && !res) {
+    if (st) return launch_one<P_FP8, CM_UPF, 4, IN_ACT, OUT_ACT, false, true>(a, s);
+    return launch_one<P_FP8, CM_UPF, 4, IN_ACT, OUT_ACT, false, false>(a, s);
+  }
+  if (a.mode == CM_S1) {
+    if (!res && st) return launch_one<P_FP8, CM_S1, 4, IN_ACT, OUT_ACT, false, true>(a, s);
+    if (res && st) return launch_one<P_FP8, CM_S1, 4, IN_ACT, OUT_ACT, true, true>(a, s);
+    if (res && !st) return launch_one<P_FP8, CM_S1, 4, IN_ACT, OUT_ACT, true, false>(a, s);
+    return launch_one<P_FP8, CM_S1, 4, IN_ACT, OUT_ACT, false, false>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
   if (a.stats && !(a.nt == 64 && a.Cout == 64 && a.cout_tiles == 1)) return hipErrorInvalidValue;
   if (a.prec == P_BF16) return dispatch_prec<P_BF16>(a, s);
   if (a.prec == P_F32) return dispatch_prec<P_F32>(a, s);
+  if (a.prec == P_FP8) return dispatch_fp8(a, s);
   return hipErrorInvalidValue;
+}
+
+int wgrad_items(int view, int N, int To, int Ho, int Wo) {
+  int th, tw;
+  if (view == CM_S2) { th = WGeo<CM_S2>::TH; tw = WGeo<CM_S2>::TW; }
+  else { th = WGeo<CM_S1>::TH; tw = WGeo<CM_S1>::TW; }
+  return N * To * ((Ho + th - 1) / th) * ((Wo + tw - 1) / tw);
+}
+
+hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s) {
+  const long long nb = 3LL * ((a.Cin + 31) / 32) * ((a.Cout + 63) / 64) * a.splits;
+  if (nb <= 0 || nb > 0x7fffffffLL || a.splits < 1) return hipErrorInvalidValue;
+  const dim3 g((unsigned)nb), b(256);
+#define TOK_WG(P, V) hipLaunchKernelGGL((wgrad_kernel<P, V>), g, b, 0, s, a)
+  if (a.prec == P_BF16) {
+    if (a.view == CM_S1) TOK_WG(P_BF16, CM_S1);
+    else if (a.view == CM_S2) TOK_WG(P_BF16, CM_S2);
+    else if (a.view == CM_UP) TOK_WG(P_BF16, CM_UP);
+    else return hipErrorInvalidValue;
+  } else {
+    if (a.view == CM_S1) TOK_WG(P_F32, CM_S1);
+    else if (a.view == CM_S2) TOK_WG(P_F32, CM_S2);
+    else if (a.view == CM_UP) TOK_WG(P_F32, CM_UP);
+    else return hipErrorInvalidValue;
+  }
+#undef TOK_WG
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const float* partial, const float* bpartial, int splits, int Cout, int Cin, float* dw,
+                               float* db, hipStream_t s) {
+  const size_t total = (size_t)Cout * Cin * 27 + Cout;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, partial, bpartial,
+                     splits, Cout, Cin, dw, db);
+  return hipGetLastError();
 }
 
 // Packed weight layout, per output-channel tile ct (nt channels):
@@ -551,77 +948,171 @@ hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
 // followed by a 3-tap kernel is, for output parity 0, tap 0 on source offset
 // -1 and taps 1+2 on offset 0; for parity 1, taps 0+1 on offset 0 and tap 2 on
 // offset +1.
+// Adjoint layout (CM_S1T), per adjoint output tile ct and weight set:
+//   [ct][set][dt][chunk][kh*3+kw][o][quad][QE]
+// with adjoint output channel o = forward input channel, adjoint input channel
+// = forward output channel, gradient frame t + dt and spatial tap (dh, dw) =
+// forward tap (2 - dh, 2 - dw).  Set 0 (output frames >= 1) uses forward tap
+// kt = 2 - dt; set 1 (output frame 0, which the causal clamp reads for every
+// t + kt <= 2) sums forward taps kt = 0 .. 2 - dt.
+//
+// The packing runs on the device (one thread per packed element), so packed
+// weights can be refreshed from a device-resident parameter vector.
 namespace {
-int fold_lo(int parity, int d) { return parity == 0 ? (d == 0 ? 0 : 1) : (d == 0 ? 0 : 2); }
-int fold_hi(int parity, int d) { return parity == 0 ? (d == 0 ? 0 : 2) : (d == 0 ? 1 : 2); }
 
-void store_elem(void* dst, size_t e, float v, int prec) {
-  if (prec == P_BF16) {
-    uint32_t u;
-    __builtin_memcpy(&u, &v, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    reinterpret_cast<uint16_t*>(dst)[e] = (uint16_t)(u >> 16);
+struct PackGeom {
+  int Cout, Cin;     // forward conv
+  int CH, QE, nt, chunks, mode;
+  int co;            // output channels of the packed kernel (Cin for the adjoint)
+  int R;             // entries of the layout's leading dimensions per output-channel tile
+};
+
+__host__ __device__ inline int fold_lo(int parity, int d) { return parity == 0 ? (d == 0 ? 0 : 1) : (d == 0 ? 0 : 2); }
+__host__ __device__ inline int fold_hi(int parity, int d) { return parity == 0 ? (d == 0 ? 0 : 2) : (d == 0 ? 1 : 2); }
+
+__device__ float pack_value(const float* __restrict__ w, const PackGeom& g, size_t e) {
+  const int x = (int)(e % g.QE); e /= g.QE;
+  const int pq = (int)(e % 4); e /= 4;
+  const int o = (int)(e % g.nt); e /= g.nt;
+  auto W = [&](int co, int ci, int kt, int kh, int kw) -> float {
+    return w[((((size_t)co * g.Cin + ci) * 3 + kt) * 3 + kh) * 3 + kw];
+  };
+  if (g.mode == CM_UPF) {
+    const int tap = (int)(e % 4); e /= 4;
+    const int phase = (int)(e % 4); e /= 4;
+    const int ck = (int)(e % g.chunks); e /= g.chunks;
+    const int dt = (int)(e % 2); e /= 2;
+    const int pt = (int)(e % 2); e /= 2;
+    const int ct = (int)e;
+    const int row = (phase * 4 + tap) * g.nt + o;
+    const int q = pq ^ swz(row);
+    const int co = ct * g.nt + o, ci = ck * g.CH + q * g.QE + x;
+    if (co >= g.Cout || ci >= g.Cin) return 0.f;
+    const int ph = phase >> 1, pw = phase & 1, dh = tap >> 1, dw = tap & 1;
+    float v = 0.f;
+    for (int kt = fold_lo(pt, dt); kt <= fold_hi(pt, dt); ++kt)
+      for (int kh = fold_lo(ph, dh); kh <= fold_hi(ph, dh); ++kh)
+        for (int kw = fold_lo(pw, dw); kw <= fold_hi(pw, dw); ++kw) v += W(co, ci, kt, kh, kw);
+    return v;
+  }
+  const int tap = (int)(e % 9); e /= 9;
+  const int ck = (int)(e % g.chunks); e /= g.chunks;
+  const int kt = (int)(e % 3); e /= 3;  // CM_S1T: gradient frame offset dt
+  const int row = tap * g.nt + o;
+  const int q = pq ^ swz(row);          // logical quad stored at physical quad pq
+  if (g.mode == CM_S1T) {
+    const int set = (int)(e % 2); e /= 2;
+    const int ct = (int)e;
+    const int oc = ct * g.nt + o, ic = ck * g.CH + q * g.QE + x;  // adjoint out / in channels
+    if (oc >= g.Cin || ic >= g.Cout) return 0.f;
+    const int dt = kt, kh = 2 - tap / 3, kw = 2 - tap % 3;
+    float v = 0.f;
+    for (int k = (set == 0 ? 2 - dt : 0); k <= 2 - dt; ++k) v += W(ic, oc, k, kh, kw);
+    return v;
+  }
+  const int ct = (int)e;
+  const int co = ct * g.nt + o, ci = ck * g.CH + q * g.QE + x;
+  if (co >= g.Cout || ci >= g.Cin) return 0.f;
+  return W(co, ci, kt, tap / 3, tap % 3);
+}
+
+// Per-output-channel fp8 scale: the largest magnitude of the channel's packed
+// (possibly folded) kernel / 448, or 1 for an all-zero channel.  One block per
+// output channel; its packed elements are, for outer index r (the layout's
+// leading dimensions after the tile) and inner index q (quad, element):
+//   e = ((ct R + r) nt + o) 4 QE + q.
+__global__ void __launch_bounds__(256) wscale_kernel(const float* __restrict__ w, PackGeom g, int R,
+                                                      float* __restrict__ scale) {
+  __shared__ float red[256];
+  const int c = blockIdx.x, ct = c / g.nt, o = c % g.nt;
+  const int inner = 4 * g.QE;
+  float m = 0.f;
+  for (int j = threadIdx.x; j < R * inner; j += 256) {
+    const int r = j / inner, q = j % inner;
+    const size_t e = (((size_t)ct * R + r) * g.nt + o) * inner + q;
+    m = fmaxf(m, fabsf(pack_value(w, g, e)));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scale[c] = red[0] > 0.f ? red[0] / kFp8Max : 1.f;
+}
+
+// Round to nearest even, as the activations' hardware conversion does.
+__device__ inline uint16_t bf16_bits_rne(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) pack_kernel(const float* __restrict__ w, PackGeom g, size_t n, void* dst,
+                                                    const float* __restrict__ wscale) {
+  if constexpr (PREC == P_FP8) {
+    // four consecutive elements (same output channel) per thread -> one 32-bit store
+    const size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (e >= n) return;
+    const size_t row = e / (4 * g.QE);  // (ct, r, o) flattened
+    const int c = (int)(row / ((size_t)g.R * g.nt)) * g.nt + (int)(row % g.nt);
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = pack_value(w, g, e + k);
+    const float inv = c < g.co ? 1.0f / wscale[c] : 0.f;
+    reinterpret_cast<uint32_t*>(dst)[e / 4] = pack_fp8x4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
   } else {
-    reinterpret_cast<float*>(dst)[e] = v;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float v = pack_value(w, g, e);
+    if constexpr (PREC == P_BF16) reinterpret_cast<uint16_t*>(dst)[e] = bf16_bits_rne(v);
+    else reinterpret_cast<float*>(dst)[e] = v;
   }
 }
+
+PackGeom pack_geom(int Cout, int Cin, int prec, int mode, size_t* elems) {
+  PackGeom g;
+  g.Cout = Cout; g.Cin = Cin; g.mode = mode;
+  g.CH = prec == P_BF16 ? 32 : (prec == P_FP8 ? 64 : 16);
+  g.QE = g.CH / 4;
+  const int co = mode == CM_S1T ? Cin : Cout;   // the adjoint maps Cout channels to Cin channels
+  const int ci = mode == CM_S1T ? Cout : Cin;
+  g.co = co;
+  g.nt = co >= 64 ? 64 : 16;
+  g.chunks = (ci + g.CH - 1) / g.CH;
+  if (mode == CM_UPF) g.R = 2 * 2 * g.chunks * 16;
+  else if (mode == CM_S1T) g.R = 2 * 3 * g.chunks * 9;
+  else g.R = 3 * g.chunks * 9;
+  const size_t tiles = (size_t)((co + g.nt - 1) / g.nt);
+  *elems = tiles * g.R * g.nt * g.CH;
+  return g;
+}
+
 }  // namespace
 
 size_t packed_conv_elems(int Cout, int Cin, int prec, int mode, int* nt_out) {
-  const int CH = prec == P_BF16 ? 32 : 16;
-  const int nt = Cout >= 64 ? 64 : 16;
-  const int tiles = (Cout + nt - 1) / nt;
-  const int chunks = (Cin + CH - 1) / CH;
-  if (nt_out) *nt_out = nt;
-  if (mode == CM_UPF) return (size_t)tiles * 2 * 2 * chunks * 16 * nt * CH;
-  return (size_t)tiles * 3 * chunks * 9 * nt * CH;
+  size_t n;
+  const PackGeom g = pack_geom(Cout, Cin, prec, mode, &n);
+  if (nt_out) *nt_out = g.nt;
+  return n;
 }
 
-void pack_conv_weights(const float* w, int Cout, int Cin, int prec, int mode, void* dst) {
-  const int CH = prec == P_BF16 ? 32 : 16;
-  const int QE = CH / 4;
-  int nt;
-  packed_conv_elems(Cout, Cin, prec, mode, &nt);
-  const int tiles = (Cout + nt - 1) / nt;
-  const int chunks = (Cin + CH - 1) / CH;
-  auto W = [&](int co, int ci, int kt, int kh, int kw) -> float {
-    if (co >= Cout || ci >= Cin) return 0.f;
-    return w[((((size_t)co * Cin + ci) * 3 + kt) * 3 + kh) * 3 + kw];
-  };
-  size_t e = 0;
-  if (mode == CM_UPF) {
-    for (int ct = 0; ct < tiles; ++ct)
-      for (int pt = 0; pt < 2; ++pt)
-        for (int dt = 0; dt < 2; ++dt)
-          for (int ck = 0; ck < chunks; ++ck)
-            for (int phase = 0; phase < 4; ++phase)
-              for (int tap = 0; tap < 4; ++tap)
-                for (int o = 0; o < nt; ++o)
-                  for (int pq = 0; pq < 4; ++pq)
-                    for (int x = 0; x < QE; ++x, ++e) {
-                      const int row = (phase * 4 + tap) * nt + o;
-                      const int q = pq ^ swz(row);
-                      const int co = ct * nt + o, ci = ck * CH + q * QE + x;
-                      const int ph = phase >> 1, pw = phase & 1, dh = tap >> 1, dw = tap & 1;
-                      float v = 0.f;
-                      for (int kt = fold_lo(pt, dt); kt <= fold_hi(pt, dt); ++kt)
-                        for (int kh = fold_lo(ph, dh); kh <= fold_hi(ph, dh); ++kh)
-                          for (int kw = fold_lo(pw, dw); kw <= fold_hi(pw, dw); ++kw) v += W(co, ci, kt, kh, kw);
-                      store_elem(dst, e, v, prec);
-                    }
-    return;
+hipError_t launch_pack_weights(const float* w, int Cout, int Cin, int prec, int mode, void* dst, float* wscale,
+                               hipStream_t s) {
+  size_t n;
+  const PackGeom g = pack_geom(Cout, Cin, prec, mode, &n);
+  if (prec == P_FP8) {
+    if (!wscale || mode == CM_S1T) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wscale_kernel, dim3(g.co), dim3(256), 0, s, w, g, g.R, wscale);
+    hipLaunchKernelGGL(pack_kernel<P_FP8>, dim3((unsigned)((n / 4 + 255) / 256)), dim3(256), 0, s, w, g, n, dst,
+                       (const float*)wscale);
+  } else {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (prec == P_BF16) hipLaunchKernelGGL(pack_kernel<P_BF16>, grid, dim3(256), 0, s, w, g, n, dst, nullptr);
+    else hipLaunchKernelGGL(pack_kernel<P_F32>, grid, dim3(256), 0, s, w, g, n, dst, nullptr);
   }
-  for (int ct = 0; ct < tiles; ++ct)
-    for (int kt = 0; kt < 3; ++kt)
-      for (int ck = 0; ck < chunks; ++ck)
-        for (int tap = 0; tap < 9; ++tap)
-          for (int o = 0; o < nt; ++o)
-            for (int pq = 0; pq < 4; ++pq)
-              for (int x = 0; x < QE; ++x, ++e) {
-                const int row = tap * nt + o;
-                const int q = pq ^ swz(row);  // logical quad stored at physical quad pq
-                store_elem(dst, e, W(ct * nt + o, ck * CH + q * QE + x, kt, tap / 3, tap % 3), prec);
-              }
+  return hipGetLastError();
 }
 
 }  // namespace tok

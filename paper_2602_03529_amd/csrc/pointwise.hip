@@ -30,7 +30,8 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
                                                            const float* __restrict__ gamma,
                                                            const float* __restrict__ beta, float eps,
                                                            float* __restrict__ scale,
-                                                           float* __restrict__ shift) {
+                                                           float* __restrict__ shift,
+                                                           float2* __restrict__ mr) {
   const int frame = blockIdx.x;
   const int g = threadIdx.x >> 3, j = threadIdx.x & 7;
   const float4* s = stats + (size_t)frame * tiles * 32;
@@ -54,6 +55,7 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
     const int c = 2 * g + j;
     const float var = q / n;
     const float rstd = 1.0f / sqrtf(var + eps);
+    if (mr && j == 0) mr[(size_t)frame * 32 + g] = make_float2(m, rstd);
     const float sc = rstd * gamma[c];
     scale[(size_t)frame * 64 + c] = sc;
     shift[(size_t)frame * 64 + c] = beta[c] - m * sc;
@@ -296,14 +298,100 @@ __global__ void __launch_bounds__(256) proj_in_kernel(const float* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// MX-FP8 producers.  One thread per (position, 32-channel block): compute the
+// 32 values, take their largest magnitude, pick the block's E8M0 scale
+// 2^e (smallest with max * 2^-e <= 448), and store 32 e4m3 bytes plus the
+// scale byte.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_fp8_block(const float* v, uint8_t* dst, uint8_t* sdst) {
+  float am = 0.f;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) am = fmaxf(am, fabsf(v[k]));
+  const int e = fp8_block_exp(am);
+  const float f = ldexpf(1.0f, -e);
+  uint32_t w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = pack_fp8x4(v[4 * k] * f, v[4 * k + 1] * f, v[4 * k + 2] * f, v[4 * k + 3] * f);
+  reinterpret_cast<uint4*>(dst)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  reinterpret_cast<uint4*>(dst)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  *sdst = (uint8_t)(e + 127);
+}
+
+// y = silu(x * scale + shift): bf16 level-0 activations (64 channels, 2
+// chunks of 32) -> MX-FP8 (1 chunk of 64 + 2 scale bytes per position).
+__global__ void __launch_bounds__(256) gn_act_fp8_kernel(const uint4* __restrict__ in, int in_Tb, int in_f0,
+                                                          uint8_t* __restrict__ out, uint8_t* __restrict__ osc,
+                                                          int out_Tb, int out_f0, int F, int HW,
+                                                          const float* __restrict__ scale,
+                                                          const float* __restrict__ shift) {
+  const int nf = blockIdx.y;  // (n, f)
+  const int n = nf / F, f = nf % F;
+  const int t = blockIdx.x * 256 + threadIdx.x;  // (position, block)
+  if (t >= HW * 2) return;
+  const int pos = t >> 1, blk = t & 1;
+  const size_t fin = (size_t)n * in_Tb + in_f0 + f, fout = (size_t)n * out_Tb + out_f0 + f;
+  const uint4* src = in + ((fin * 2 + blk) * HW + pos) * 4;
+  const float* sc = scale + (size_t)nf * 64 + blk * 32;
+  const float* sh = shift + (size_t)nf * 64 + blk * 32;
+  float v[32];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint4 u = src[q];
+    const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = q * 8 + 2 * k;
+      v[c] = silu_f(bf16_lo(w4[k]) * sc[c] + sh[c]);
+      v[c + 1] = silu_f(bf16_hi(w4[k]) * sc[c + 1] + sh[c + 1]);
+    }
+  }
+  store_fp8_block(v, out + (fout * HW + pos) * kChunkBytes + blk * 32, osc + (fout * HW + pos) * 2 + blk);
+}
+
+// codes (6) -> 128 channels of MX-FP8 (2 chunks, 4 scale bytes per position).
+__global__ void __launch_bounds__(256) proj_in_fp8_kernel(const float* __restrict__ codes, int N, int T2, int t0,
+                                                           int F, int HW, const float* __restrict__ wpin,
+                                                           const float* __restrict__ bpin, uint8_t* __restrict__ out,
+                                                           uint8_t* __restrict__ osc, int Tb, int f0) {
+  __shared__ float w[128 * 6];
+  __shared__ float bsh[128];
+  for (int e = threadIdx.x; e < 128 * 6; e += blockDim.x) w[e] = wpin[e];
+  for (int e = threadIdx.x; e < 128; e += blockDim.x) bsh[e] = bpin[e];
+  __syncthreads();
+  const size_t ntok = (size_t)N * F * HW;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ntok * 4) return;
+  const size_t lt = gid / 4;
+  const int blk = (int)(gid % 4);  // 32-channel block: chunk blk / 2, half blk % 2
+  const size_t nf = lt / HW, hw = lt % HW;
+  const int n = (int)(nf / F), f = (int)(nf % F);
+  const size_t tok = ((size_t)n * T2 + t0 + f) * HW + hw;
+  const size_t frame = (size_t)n * Tb + f0 + f;
+  float c6[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) c6[c] = codes[tok * 6 + c];
+  float y[32];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    const int o = blk * 32 + e;
+    float a = bsh[o];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a = fmaf(w[o * 6 + c], c6[c], a);
+    y[e] = a;
+  }
+  const size_t ck = frame * 2 + blk / 2;
+  store_fp8_block(y, out + (ck * HW + hw) * kChunkBytes + (blk % 2) * 32, osc + (ck * HW + hw) * 2 + (blk % 2));
+}
+
 inline unsigned blocks_for(size_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
 
 hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const float* gamma, const float* beta,
-                              float eps, float* scale, float* shift, hipStream_t s) {
+                              float eps, float* scale, float* shift, float2* mr, hipStream_t s) {
   hipLaunchKernelGGL(gn_finalize_kernel, dim3(frames), dim3(256), 0, s, stats, tiles, gamma, beta, eps, scale,
-                     shift);
+                     shift, mr);
   return hipGetLastError();
 }
 
@@ -320,6 +408,25 @@ hipError_t launch_gn_act(const void* in, int in_Tb, int in_f0, void* out, int ou
   else
     hipLaunchKernelGGL(gn_act_kernel<P_F32>, grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(in), in_Tb, in_f0,
                        reinterpret_cast<uint4*>(out), out_Tb, out_f0, F, HW, scale, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_gn_act_fp8(const void* in, int in_Tb, int in_f0, uint8_t* out, uint8_t* out_scale, int out_Tb,
+                             int out_f0, int N, int F, int HW, const float* scale, const float* shift, hipStream_t s) {
+  const long long frames = (long long)N * F;
+  if (frames > 65535 || F < 1 || in_f0 < 0 || in_f0 + F > in_Tb || out_f0 < 0 || out_f0 + F > out_Tb)
+    return hipErrorInvalidValue;
+  const dim3 grid(blocks_for((size_t)HW * 2, 256), (unsigned)frames);
+  hipLaunchKernelGGL(gn_act_fp8_kernel, grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(in), in_Tb, in_f0, out,
+                     out_scale, out_Tb, out_f0, F, HW, scale, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_proj_in_fp8(const float* codes, int N, int T2, int t0, int F, int HW, const float* w, const float* b,
+                              uint8_t* out, uint8_t* out_scale, int Tb, int f0, hipStream_t s) {
+  const size_t n = (size_t)N * F * HW * 4;
+  hipLaunchKernelGGL(proj_in_fp8_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, N, T2, t0, F, HW, w, b, out,
+                     out_scale, Tb, f0);
   return hipGetLastError();
 }
 

@@ -9,40 +9,40 @@
 #include <vector>
 
 #include "tok.h"
-#include "tok_internal.h"
+#include "tok_model.h"
 
 using namespace tok;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-tok_status fail(tok_status s, const std::string& msg) {
+tok_status tok::fail(tok_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
 
-#define TOK_HIP(call)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(TOK_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
-  } while (0)
+FsqConst tok::make_fsq_const() {
+  const int levels[6] = {8, 8, 8, 5, 5, 5};
+  FsqConst f;
+  int basis = 1;
+  for (int c = 0; c < 6; ++c) {
+    const double L = levels[c];
+    const double h = (L - 1.0) * (1.0 - 1e-3) / 2.0;
+    const double o = (levels[c] % 2 == 0) ? 0.5 : 0.0;
+    const double d = std::floor(L / 2.0);
+    f.h[c] = (float)h;
+    f.o[c] = (float)o;
+    f.s[c] = (float)std::atanh(o / h);
+    f.d[c] = (float)d;
+    f.inv_d[c] = (float)(1.0 / d);
+    f.basis[c] = basis;
+    basis *= levels[c];
+  }
+  return f;
+}
 
-// ---------------------------------------------------------------------------
-// Parameter table (canonical blob order, see tok_weight_count in tok.h)
-// ---------------------------------------------------------------------------
-enum LayerId {
-  L_CONV_IN = 0, L_E_RB1_A, L_E_RB1_B, L_E_RB2_A, L_E_RB2_B, L_DOWN1, L_DOWN2, L_PROJ,
-  L_PROJ_IN, L_UP2, L_UP1, L_D_RB1_A, L_D_RB1_B, L_D_RB2_A, L_D_RB2_B, L_CONV_OUT, L_COUNT
-};
-enum NormId { N_E_RB1_A = 0, N_E_RB1_B, N_E_RB2_A, N_E_RB2_B, N_D_RB1_A, N_D_RB1_B, N_D_RB2_A, N_D_RB2_B, N_COUNT };
-
-struct ConvSpec { int cout, cin, k; };
-const ConvSpec kConv[L_COUNT] = {
-    {64, 3, 3},   {64, 64, 3},  {64, 64, 3},  {64, 64, 3},  {64, 64, 3},  {128, 64, 3},
-    {128, 128, 3}, {6, 128, 1}, {128, 6, 1},  {128, 128, 3}, {64, 128, 3}, {64, 64, 3},
-    {64, 64, 3},  {64, 64, 3},  {64, 64, 3},  {3, 64, 3}};
+namespace {
 
 struct BlobItem { int is_conv; int id; };  // conv layer or norm
 // module order: conv_in, rb1(gn_a, a, gn_b, b), rb2, down1, down2, proj, proj_in, up2, up1, rb1, rb2, conv_out
@@ -68,73 +68,9 @@ size_t blob_count() {
   return n;
 }
 
-// Addressing mode of each 3x3x3 layer.
-int conv_mode(int l) {
-  if (l == L_DOWN1 || l == L_DOWN2) return CM_S2;
-  if (l == L_UP2 || l == L_UP1) return CM_UPF;
-  return CM_S1;
-}
-
-constexpr float kGnEps = 1e-6f;
-const int kLevels[6] = {8, 8, 8, 5, 5, 5};
-
-FsqConst make_fsq_const() {
-  FsqConst f;
-  int basis = 1;
-  for (int c = 0; c < 6; ++c) {
-    const double L = kLevels[c];
-    const double h = (L - 1.0) * (1.0 - 1e-3) / 2.0;
-    const double o = (kLevels[c] % 2 == 0) ? 0.5 : 0.0;
-    const double d = std::floor(L / 2.0);
-    f.h[c] = (float)h;
-    f.o[c] = (float)o;
-    f.s[c] = (float)std::atanh(o / h);
-    f.d[c] = (float)d;
-    f.inv_d[c] = (float)(1.0 / d);
-    f.basis[c] = basis;
-    basis *= kLevels[c];
-  }
-  return f;
-}
-
 }  // namespace
 
-struct ProfRec {
-  int id;
-  hipEvent_t a, b;
-};
-
-struct tok_model {
-  bool profiling = false;
-  std::vector<ProfRec> prof;
-  int device = 0;
-  int prec = P_BF16;
-  void* mem = nullptr;          // one device allocation holding everything below
-  const void* wpk[L_COUNT] = {};  // packed k=3 weights
-  int nt[L_COUNT] = {};
-  const float* bias[L_COUNT] = {};
-  const float* w1x1[L_COUNT] = {};  // plain fp32 [Cout][Cin] for the 1x1x1 layers
-  const float* gamma[N_COUNT] = {};
-  const float* beta[N_COUNT] = {};
-};
-
 namespace {
-
-struct Dims {
-  int N, T, H, W, T1, H1, W1, T2, H2, W2;
-};
-
-bool make_dims(int N, int T, int H, int W, Dims* d) {
-  if (N < 1 || T < 1 || H < 4 || W < 4) return false;
-  if ((T - 1) % 4 != 0 || H % 4 != 0 || W % 4 != 0) return false;
-  d->N = N; d->T = T; d->H = H; d->W = W;
-  d->T1 = (T - 1) / 2 + 1; d->H1 = H / 2; d->W1 = W / 2;
-  d->T2 = (d->T1 - 1) / 2 + 1; d->H2 = H / 4; d->W2 = W / 4;
-  return true;
-}
-
-inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace plan for processing a clip in causal temporal chunks of CL latent
 // frames (CL = T2: the whole clip at once).  Chunk [L0, L1) of latent frames
@@ -220,41 +156,21 @@ struct Win {
   int Tb, g0, first, count;
 };
 
-constexpr int K_GN_FINAL = 16;
-constexpr int K_GN_ACT = 17;
-constexpr int K_IDS = 18;
 const char* kKernelNames[K_IDS] = {
     "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
     "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
-    "dec.rb2.b", "dec.conv_out", "gn_finalize", "gn_silu"};
-
-// Records an event pair around the launches made while it is alive (profiling only).
-struct Timed {
-  tok_model* m;
-  hipStream_t s;
-  ProfRec r;
-  bool on;
-  Timed(const tok_model* mc, int id, hipStream_t st) : m(const_cast<tok_model*>(mc)), s(st), on(mc->profiling) {
-    if (!on) return;
-    r.id = id;
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) { on = false; return; }
-    hipEventRecord(r.a, s);
-  }
-  ~Timed() {
-    if (!on) return;
-    hipEventRecord(r.b, s);
-    m->prof.push_back(r);
-  }
-};
+    "dec.rb2.b", "dec.conv_out", "gn_finalize", "gn_silu", "bwd.dgrad", "bwd.wgrad", "bwd.gn_silu",
+    "bwd.other"};
 
 // Conv launch: reads the whole input buffer `iw` (its frames are addressed
 // through their global numbers) and writes the window `ow` of the output.
 tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_kind, int N, const Win& iw, int Hi,
                 int Wi, int Cin, void* out, int out_kind, const Win& ow, int Ho, int Wo, const void* resid,
-                float4* stats, hipStream_t s) {
+                float4* stats, hipStream_t s, const uint8_t* in_scale = nullptr, uint8_t* out_scale = nullptr) {
   ConvLaunch a;
   std::memset(&a, 0, sizeof(a));
-  const int CH = m->prec == P_BF16 ? 32 : 16;
+  const int CH = m->prec == P_BF16 ? 32 : (m->prec == P_FP8 ? 64 : 16);  // input chunking
+  const int CHo = out_kind == OUT_FP8 ? 64 : (m->prec == P_F32 ? 16 : 32);
   a.in = in;
   a.N = N; a.Ti = iw.Tb; a.Hi = Hi; a.Wi = Wi;
   a.gi0 = iw.g0;
@@ -269,8 +185,11 @@ tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_
   a.resid = resid;
   a.To = ow.count; a.Ho = Ho; a.Wo = Wo;
   a.To_buf = ow.Tb; a.out_f0 = ow.first; a.go0 = ow.g0 + ow.first;
-  a.out_chunks = cdiv(a.Cout, CH);
+  a.out_chunks = cdiv(a.Cout, CHo);
   a.stats = stats;
+  a.in_scale = in_scale;
+  a.out_scale = out_scale;
+  a.wscale = m->wscale[layer];
   int th, tw;
   conv_tile(mode, &th, &tw);
   a.tiles_h = cdiv(Ho, th);
@@ -291,7 +210,7 @@ tok_status gn_silu(const tok_model* m, int norm, const Ws& w, int N, const void*
   {
     Timed tm(m, K_GN_FINAL, s);
     const hipError_t e = launch_gn_finalize(w.stats(), N * iw.count, tiles, m->gamma[norm], m->beta[norm], kGnEps,
-                                            w.sc(), w.sh(), s);
+                                            w.sc(), w.sh(), nullptr, s);
     if (e != hipSuccess) return fail(TOK_EDEVICE, std::string("gn_finalize: ") + hipGetErrorString(e));
   }
   Timed tm(m, K_GN_ACT, s);
@@ -301,11 +220,6 @@ tok_status gn_silu(const tok_model* m, int norm, const Ws& w, int N, const void*
   return TOK_OK;
 }
 
-#define TOK_TRY(x)                 \
-  do {                             \
-    tok_status s_ = (x);           \
-    if (s_ != TOK_OK) return s_;   \
-  } while (0)
 
 // Copy `frames` frames per clip between a buffer window position and a cache
 // slot (dir > 0: buffer -> cache, else cache -> buffer).
@@ -410,6 +324,154 @@ DropArgs make_drop(const tok_drop_desc* dd) {
 
 }  // namespace
 
+namespace {
+
+// Layout of the model's device allocation (bytes), computed from the layer table.
+// An fp8 model holds the decoder only (packed e4m3 kernels with per-channel
+// scales) and no adjoint kernels; f32 / bf16 models hold everything.
+struct ModelLayout {
+  size_t blob, wpk[L_COUNT], wpkT[L_COUNT], wsc[L_COUNT], w1T[L_COUNT], zeros, total;
+  int nt[L_COUNT], ntT[L_COUNT];
+  bool has[L_COUNT], hasT;
+};
+
+ModelLayout model_layout(int P) {
+  const size_t es = P == P_BF16 ? 2 : (P == P_FP8 ? 1 : 4);
+  ModelLayout L;
+  std::memset(&L, 0, sizeof(L));
+  L.hasT = P != P_FP8;
+  size_t off = 0;
+  L.blob = off;
+  off = align256(off + blob_count() * 4);
+  for (int l = 0; l < L_COUNT; ++l) {
+    const ConvSpec& c = kConv[l];
+    L.has[l] = P != P_FP8 || is_decoder_layer(l);
+    if (c.k == 3) {
+      if (L.has[l]) {
+        L.wpk[l] = off;
+        off = align256(off + packed_conv_elems(c.cout, c.cin, P, conv_mode(l), &L.nt[l]) * es);
+      }
+      if (P == P_FP8 && L.has[l]) {
+        L.wsc[l] = off;
+        off = align256(off + (size_t)c.cout * 4);
+      }
+      if (L.hasT) {
+        L.wpkT[l] = off;
+        off = align256(off + packed_conv_elems(c.cout, c.cin, P, CM_S1T, &L.ntT[l]) * es);
+      }
+    } else {
+      L.w1T[l] = off;
+      off = align256(off + (size_t)c.cout * c.cin * 4);
+    }
+  }
+  L.zeros = off;
+  off = align256(off + 128 * 4);
+  L.total = off;
+  return L;
+}
+
+// Packs every kernel of the model from its blob (stream-ordered).
+tok_status repack(tok_model* m, hipStream_t s) {
+  for (int l = 0; l < L_COUNT; ++l) {
+    const ConvSpec& c = kConv[l];
+    const float* w = m->blob + m->w_off[l];
+    if (c.k == 3) {
+      if (m->wpk[l]) TOK_HIP(launch_pack_weights(w, c.cout, c.cin, m->prec, conv_mode(l), m->wpk[l], m->wscale[l], s));
+      if (m->wpkT[l]) TOK_HIP(launch_pack_weights(w, c.cout, c.cin, m->prec, CM_S1T, m->wpkT[l], nullptr, s));
+    } else {
+      TOK_HIP(launch_transpose(w, c.cout, c.cin, m->w1x1T[l], s));
+    }
+  }
+  return TOK_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// fp8 decoder (whole clips).  MX-FP8 activations feed every conv; the
+// residual stream and the GroupNorm inputs stay bf16:
+//   P  = proj_in(codes)                      MX-FP8, level 2
+//   U2 = up2(P)                              MX-FP8, level 1
+//   A  = up1(U2)                             bf16 (+ GN partials), level 0
+//   RB: S = silu(gn_a A) (MX-FP8); C = conv_a(S) (bf16 + GN partials);
+//       S = silu(gn_b C); A = A + conv_b(S)  (bf16, + GN partials)
+//   last RB: R2 = A + conv_b(S) written as MX-FP8 (into C's space)
+//   x_hat = conv_out(R2)
+// ---------------------------------------------------------------------------
+struct Fp8Plan {
+  size_t P, Psc, U2, U2sc, A, S, Ssc, C, Csc, stats, sc, sh, total;
+};
+
+Fp8Plan make_fp8_plan(const Dims& d) {
+  Fp8Plan p;
+  const size_t n0 = (size_t)d.N * d.T * d.H * d.W, n1 = (size_t)d.N * d.T1 * d.H1 * d.W1;
+  const size_t n2 = (size_t)d.N * d.T2 * d.H2 * d.W2;
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t r = o; o += align256(b); return r; };
+  p.P = take(n2 * 128); p.Psc = take(n2 * 4);
+  p.U2 = take(n1 * 128); p.U2sc = take(n1 * 4);
+  p.A = take(n0 * 128);
+  p.S = take(n0 * 64); p.Ssc = take(n0 * 2);
+  p.C = take(n0 * 128); p.Csc = take(n0 * 2);
+  p.stats = take((size_t)d.N * d.T * cdiv(d.H, 8) * cdiv(d.W, 64) * 32 * sizeof(float4));
+  p.sc = take((size_t)d.N * d.T * 64 * 4); p.sh = take((size_t)d.N * d.T * 64 * 4);
+  p.total = o;
+  return p;
+}
+
+tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xhat, void* ws, size_t ws_bytes,
+                      hipStream_t s) {
+  const Fp8Plan p = make_fp8_plan(d);
+  if (p.total > ws_bytes)
+    return fail(TOK_EWORKSPACE, "fp8 decode workspace needs " + std::to_string(p.total) + " bytes");
+  char* b = static_cast<char*>(ws);
+  auto at = [&](size_t off) { return b + off; };
+  auto u8 = [&](size_t off) { return reinterpret_cast<uint8_t*>(b + off); };
+  float4* stats = reinterpret_cast<float4*>(at(p.stats));
+  float* sc = reinterpret_cast<float*>(at(p.sc));
+  float* sh = reinterpret_cast<float*>(at(p.sh));
+  const int N = d.N, T = d.T, H = d.H, W = d.W;
+  const Win w0{T, 0, 0, T}, w1{d.T1, 0, 0, d.T1}, w2{d.T2, 0, 0, d.T2};
+  {
+    Timed tm(m, L_PROJ_IN, s);
+    TOK_HIP(launch_proj_in_fp8(codes, N, d.T2, 0, d.T2, d.H2 * d.W2, m->w1x1[L_PROJ_IN], m->bias[L_PROJ_IN],
+                               u8(p.P), u8(p.Psc), d.T2, 0, s));
+  }
+  TOK_TRY(conv(m, L_UP2, CM_UPF, at(p.P), IN_ACT, N, w2, d.H2, d.W2, 128, at(p.U2), OUT_FP8, w1, d.H1, d.W1, nullptr,
+               nullptr, s, u8(p.Psc), u8(p.U2sc)));
+  TOK_TRY(conv(m, L_UP1, CM_UPF, at(p.U2), IN_ACT, N, w1, d.H1, d.W1, 128, at(p.A), OUT_ACT, w0, H, W, nullptr, stats,
+               s, u8(p.U2sc)));
+  const int tiles = cdiv(H, 8) * cdiv(W, 64);
+  auto gn = [&](int norm, const void* in) -> tok_status {
+    {
+      Timed tm(m, K_GN_FINAL, s);
+      TOK_HIP(launch_gn_finalize(stats, N * T, tiles, m->gamma[norm], m->beta[norm], kGnEps, sc, sh, nullptr, s));
+    }
+    Timed tm(m, K_GN_ACT, s);
+    TOK_HIP(launch_gn_act_fp8(in, T, 0, u8(p.S), u8(p.Ssc), T, 0, N, T, H * W, sc, sh, s));
+    return TOK_OK;
+  };
+  for (int r = 0; r < 2; ++r) {
+    const int la = L_D_RB1_A + 2 * r, na = N_D_RB1_A + 2 * r;
+    TOK_TRY(gn(na, at(p.A)));
+    TOK_TRY(conv(m, la, CM_S1, at(p.S), IN_ACT, N, w0, H, W, 64, at(p.C), OUT_ACT, w0, H, W, nullptr, stats, s,
+                 u8(p.Ssc)));
+    TOK_TRY(gn(na + 1, at(p.C)));
+    if (r == 0)
+      TOK_TRY(conv(m, la + 1, CM_S1, at(p.S), IN_ACT, N, w0, H, W, 64, at(p.A), OUT_ACT, w0, H, W, at(p.A), stats, s,
+                   u8(p.Ssc)));
+    else
+      TOK_TRY(conv(m, la + 1, CM_S1, at(p.S), IN_ACT, N, w0, H, W, 64, at(p.C), OUT_FP8, w0, H, W, at(p.A), nullptr,
+                   s, u8(p.Ssc), u8(p.Csc)));
+  }
+  return conv(m, L_CONV_OUT, CM_S1, at(p.C), IN_ACT, N, w0, H, W, 64, xhat, OUT_RGB32, w0, H, W, nullptr, nullptr, s,
+              u8(p.Csc));
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t tok_weight_count(void) { return blob_count(); }
@@ -466,91 +528,84 @@ tok_status tok_model_create(const float* host_weights, size_t n_floats, tok_prec
   if (!host_weights || !out) return fail(TOK_EINVAL, "null argument");
   if (n_floats != blob_count()) return fail(TOK_EINVAL, "weight blob has " + std::to_string(n_floats) +
                                                            " floats, expected " + std::to_string(blob_count()));
-  if (prec != TOK_F32 && prec != TOK_BF16) return fail(TOK_EUNSUPPORTED, "precision not available");
-  const int P = prec == TOK_BF16 ? P_BF16 : P_F32;
-  const size_t es = P == P_BF16 ? 2 : 4;
+  if (prec != TOK_F32 && prec != TOK_BF16 && prec != TOK_FP8_E4M3) return fail(TOK_EUNSUPPORTED, "unknown precision");
+  const int P = prec == TOK_BF16 ? P_BF16 : (prec == TOK_FP8_E4M3 ? P_FP8 : P_F32);
+  const ModelLayout L = model_layout(P);
 
-  // Host staging: compute the device layout and fill one host buffer.
-  std::vector<size_t> conv_off(L_COUNT), bias_off(L_COUNT), w1_off(L_COUNT), g_off(N_COUNT), b_off(N_COUNT);
-  std::vector<const float*> src_w(L_COUNT), src_b(L_COUNT), src_g(N_COUNT), src_be(N_COUNT);
-  const float* cur = host_weights;
+  tok_model* m = new (std::nothrow) tok_model;
+  if (!m) return fail(TOK_ENOMEM, "host allocation failed");
+  m->device = device;
+  m->prec = P;
+  // blob offsets of every tensor, in canonical order
+  size_t cur = 0;
   for (const auto& it : kOrder) {
     if (it.is_conv) {
       const ConvSpec& c = kConv[it.id];
-      src_w[it.id] = cur;
+      m->w_off[it.id] = cur;
       cur += (size_t)c.cout * c.cin * c.k * c.k * c.k;
-      src_b[it.id] = cur;
+      m->b_off[it.id] = cur;
       cur += c.cout;
     } else {
-      src_g[it.id] = cur; cur += 64;
-      src_be[it.id] = cur; cur += 64;
+      m->g_off[it.id] = cur; cur += 64;
+      m->be_off[it.id] = cur; cur += 64;
     }
-  }
-  size_t off = 0;
-  int nt[L_COUNT] = {};
-  for (int l = 0; l < L_COUNT; ++l) {
-    const ConvSpec& c = kConv[l];
-    if (c.k == 3) {
-      conv_off[l] = off;
-      off = align256(off + packed_conv_elems(c.cout, c.cin, P, conv_mode(l), &nt[l]) * es);
-    } else {
-      w1_off[l] = off;
-      off = align256(off + (size_t)c.cout * c.cin * 4);
-    }
-    bias_off[l] = off;
-    off = align256(off + (size_t)c.cout * 4);
-  }
-  for (int n = 0; n < N_COUNT; ++n) {
-    g_off[n] = off; off = align256(off + 64 * 4);
-    b_off[n] = off; off = align256(off + 64 * 4);
-  }
-  std::vector<char> host(off, 0);
-  for (int l = 0; l < L_COUNT; ++l) {
-    const ConvSpec& c = kConv[l];
-    if (c.k == 3) pack_conv_weights(src_w[l], c.cout, c.cin, P, conv_mode(l), host.data() + conv_off[l]);
-    else std::memcpy(host.data() + w1_off[l], src_w[l], (size_t)c.cout * c.cin * 4);
-    std::memcpy(host.data() + bias_off[l], src_b[l], (size_t)c.cout * 4);
-  }
-  for (int n = 0; n < N_COUNT; ++n) {
-    std::memcpy(host.data() + g_off[n], src_g[n], 64 * 4);
-    std::memcpy(host.data() + b_off[n], src_be[n], 64 * 4);
   }
 
   int prev = 0;
-  TOK_HIP(hipGetDevice(&prev));
-  TOK_HIP(hipSetDevice(device));
-  void* mem = nullptr;
-  if (hipMalloc(&mem, off) != hipSuccess) {
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+    delete m;
+    return fail(TOK_EDEVICE, "cannot select device " + std::to_string(device));
+  }
+  tok_status st = TOK_OK;
+  if (hipMalloc(&m->mem, L.total) != hipSuccess) {
+    m->mem = nullptr;
+    st = fail(TOK_ENOMEM, "hipMalloc of model weights failed");
+  }
+  if (st == TOK_OK) {
+    char* base = static_cast<char*>(m->mem);
+    m->blob = reinterpret_cast<float*>(base + L.blob);
+    for (int l = 0; l < L_COUNT; ++l) {
+      if (kConv[l].k == 3) {
+        m->wpk[l] = L.has[l] ? base + L.wpk[l] : nullptr;
+        m->wpkT[l] = L.hasT ? base + L.wpkT[l] : nullptr;
+        m->wscale[l] = P == P_FP8 && L.has[l] ? reinterpret_cast<float*>(base + L.wsc[l]) : nullptr;
+        m->nt[l] = L.nt[l];
+        m->ntT[l] = L.ntT[l];
+      } else {
+        m->w1x1[l] = m->blob + m->w_off[l];
+        m->w1x1T[l] = reinterpret_cast<float*>(base + L.w1T[l]);
+      }
+      m->bias[l] = m->blob + m->b_off[l];
+    }
+    for (int n = 0; n < N_COUNT; ++n) {
+      m->gamma[n] = m->blob + m->g_off[n];
+      m->beta[n] = m->blob + m->be_off[n];
+    }
+    m->zeros = reinterpret_cast<const float*>(base + L.zeros);
+    hipError_t e = hipMemset(base + L.zeros, 0, 128 * 4);
+    if (e == hipSuccess) e = hipMemcpy(m->blob, host_weights, n_floats * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = fail(TOK_EDEVICE, std::string("weight upload: ") + hipGetErrorString(e));
+    if (st == TOK_OK) st = repack(m, nullptr);
+    if (st == TOK_OK) {
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) st = fail(TOK_EDEVICE, std::string("weight packing: ") + hipGetErrorString(e));
+    }
+  }
+  if (st != TOK_OK) {
+    if (m->mem) hipFree(m->mem);
+    delete m;
     hipSetDevice(prev);
-    return fail(TOK_ENOMEM, "hipMalloc of model weights failed");
+    return st;
   }
-  hipError_t e = hipMemcpy(mem, host.data(), off, hipMemcpyHostToDevice);
   hipSetDevice(prev);
-  if (e != hipSuccess) {
-    hipFree(mem);
-    return fail(TOK_EDEVICE, std::string("weight upload: ") + hipGetErrorString(e));
-  }
-  tok_model* m = new (std::nothrow) tok_model;
-  if (!m) {
-    hipFree(mem);
-    return fail(TOK_ENOMEM, "host allocation failed");
-  }
-  m->device = device;
-  m->prec = P;
-  m->mem = mem;
-  char* base = static_cast<char*>(mem);
-  for (int l = 0; l < L_COUNT; ++l) {
-    if (kConv[l].k == 3) m->wpk[l] = base + conv_off[l];
-    else m->w1x1[l] = reinterpret_cast<const float*>(base + w1_off[l]);
-    m->bias[l] = reinterpret_cast<const float*>(base + bias_off[l]);
-    m->nt[l] = nt[l];
-  }
-  for (int n = 0; n < N_COUNT; ++n) {
-    m->gamma[n] = reinterpret_cast<const float*>(base + g_off[n]);
-    m->beta[n] = reinterpret_cast<const float*>(base + b_off[n]);
-  }
   *out = m;
   return TOK_OK;
+}
+
+tok_status tok_model_set_weights(tok_model* m, const float* weights, hipStream_t s) {
+  if (!m || !weights) return fail(TOK_EINVAL, "null argument");
+  TOK_HIP(hipMemcpyAsync(m->blob, weights, blob_count() * 4, hipMemcpyDeviceToDevice, s));
+  return repack(m, s);
 }
 
 void tok_model_destroy(tok_model* m) {
@@ -569,6 +624,12 @@ tok_status tok_workspace_size(const tok_model* m, int N, int T, int H, int W, in
   if (kind < TOK_WS_ENCODE || kind > TOK_WS_ROUNDTRIP) return fail(TOK_EINVAL, "bad workspace kind");
   Dims d;
   if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
+  if (m->prec == P_FP8) {
+    if (kind != TOK_WS_DECODE || (what & TOK_WS_STREAM))
+      return fail(TOK_EUNSUPPORTED, "fp8 models decode whole clips only");
+    *bytes = make_fp8_plan(d).total;
+    return TOK_OK;
+  }
   *bytes = make_plan(d, m->prec, (what & TOK_WS_STREAM) ? 1 : d.T2).total;
   return TOK_OK;
 }
@@ -578,6 +639,7 @@ tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W
                       hipStream_t s) {
   if (!m || !x || !ws) return fail(TOK_EINVAL, "null argument");
   if (!valid_drop(drop)) return fail(TOK_EINVAL, "bad drop descriptor");
+  if (m->prec == P_FP8) return fail(TOK_EUNSUPPORTED, "fp8 models hold the decoder only");
   Dims d;
   if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
   Plan p;
@@ -636,6 +698,7 @@ tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, i
   if (T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
   Dims d;
   if (!make_dims(N, 4 * (T2 - 1) + 1, 4 * H2, 4 * W2, &d)) return fail(TOK_ESHAPE, "bad latent shape");
+  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s);
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))
     return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");

@@ -30,6 +30,26 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
+// ---- fp8 e4m3 (OCP) with E8M0 block scales ---------------------------------
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+constexpr float kFp8Max = 448.0f;
+
+// Exponent e of the smallest power of two with amax * 2^-e <= 448 (0 for an
+// all-zero block), clamped to the E8M0 range; the stored scale byte is e + 127.
+__device__ __forceinline__ int fp8_block_exp(float amax) {
+  if (!(amax > 0.f)) return 0;
+  const uint32_t b = __float_as_uint(amax * (1.0f / kFp8Max));
+  int e = (int)((b >> 23) & 255u) - 127;
+  if (b & 0x7fffffu) e += 1;
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+// Four floats (already scaled into [-448, 448]) -> four e4m3 bytes, element 0 lowest.
+__device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
+}
+
 __device__ __forceinline__ float silu_f(float x) {
   return x * __builtin_amdgcn_rcpf(1.0f + __expf(-x));
 }

@@ -14,12 +14,52 @@ namespace tok {
 // a chunk is one contiguous run of memory.
 constexpr int kChunkBytes = 64;
 
-enum Prec { P_F32 = 0, P_BF16 = 1 };
+// P_FP8: conv inputs and weights in fp8 e4m3 (OCP) on the scaled MFMA, fp32
+// accumulate; see "MX-FP8 activations" below.
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 // CM_UP: nearest x2 upsample folded into the halo addressing (27 taps);
 // CM_UPF: the same operation in polyphase form (8 folded taps per output).
-enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3 };
+// CM_S1T: the adjoint (input gradient) of a stride-1 causal conv: anti-causal
+// in time, spatially flipped, channels transposed; output frame 0 uses the
+// temporal taps folded by the causal clamp (frame 0 is read three times).
+enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3, CM_S1T = 4 };
 enum InKind { IN_ACT = 0, IN_U8 = 1 };
-enum OutKind { OUT_ACT = 0, OUT_RGB32 = 1 };
+// OUT_ACT: chunked activations of the kernel's output precision (bf16 for
+// P_FP8 kernels); OUT_FP8: MX-FP8 activations; OUT_RGB32: float NDHWC (3 ch).
+enum OutKind { OUT_ACT = 0, OUT_RGB32 = 1, OUT_FP8 = 2 };
+
+// MX-FP8 activations (the inputs of the P_FP8 convs): e4m3 values in the
+// chunked layout with 64 channels per 64-byte chunk, plus a scale plane
+// [N][T][C/64][H][W][2] of E8M0 bytes, one per (position, 32 channels): the
+// value of an element is e4m3 * 2^(scale - 127).  The scale of a block is the
+// smallest power of two that brings its largest magnitude to <= 448, so no
+// element saturates.  The MFMA applies these scales itself (one per lane and
+// 32-element K block).
+
+// Weight gradient of a causal 3x3x3 conv (whole clips, no windows):
+//   dW[o][i][kt][kh][kw] = sum over output positions p of dy[p][o] * x~[p + tap][i]
+// where x~ is the conv's input seen through `view` (CM_S1 stride 1, CM_S2
+// stride 2, CM_UP nearest x2 upsampled); with bpartial set, also the bias
+// gradient db[o] = sum_p dy[p][o].  Each block reduces a share (split) of the
+// output positions for one (temporal tap, 32 input channels, 64 output
+// channels); partials [split][kt][9][Cout][Cin] and [split][Cout] are summed in
+// split order by launch_wgrad_reduce into the canonical [Cout][Cin][3][3][3]
+// layout, so the result does not depend on scheduling.
+struct WgradLaunch {
+  const void* x;      // chunked activations (Cin channels)
+  int N, Ti, Hi, Wi, x_chunks;
+  const void* dy;     // chunked gradients (Cout channels)
+  int To, Ho, Wo, dy_chunks;
+  int Cout, Cin;
+  int view, prec;
+  int splits;
+  float* partial;     // [splits][3][9][Cout][Cin]
+  float* bpartial;    // [splits][Cout] or null
+};
+int wgrad_items(int view, int N, int To, int Ho, int Wo);
+hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s);
+hipError_t launch_wgrad_reduce(const float* partial, const float* bpartial, int splits, int Cout, int Cin, float* dw,
+                               float* db, hipStream_t s);
 
 // Frames are addressed in windows so that a clip can be processed in causal
 // temporal chunks: a buffer holds Tb frames per clip, its frame 0 is global
@@ -46,6 +86,11 @@ struct ConvLaunch {
   float4* stats;         // optional per-tile GroupNorm partials [N][To][tiles][32]
   int tiles_h, tiles_w;
   int mode, in_kind, out_kind, prec;
+  // P_FP8 only: input scale plane, output scale plane (OUT_FP8), per-output-
+  // channel weight scales [Cout]
+  const uint8_t* in_scale;
+  uint8_t* out_scale;
+  const float* wscale;
 };
 
 // Tile geometry per mode (output rows x cols per workgroup).
@@ -56,15 +101,23 @@ inline void conv_tile(int mode, int* th, int* tw) {
 
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s);
 
-// Host-side packing of a [Cout][Cin][3][3][3] float kernel into the layout the
-// conv kernel streams through LDS (see conv3d.hip).  Returns element count.
+// Packing of a device-resident [Cout][Cin][3][3][3] float kernel into the
+// layout the conv kernel streams through LDS (see conv3d.hip), on the device.
+// packed_conv_elems returns the element count and the output-channel tile.
+// For mode CM_S1T, (Cout, Cin) are the forward conv's; the packed kernel maps
+// Cout-channel gradients to Cin-channel gradients.
 size_t packed_conv_elems(int Cout, int Cin, int prec, int mode, int* nt_out);
-void pack_conv_weights(const float* w, int Cout, int Cin, int prec, int mode, void* dst);
+// For P_FP8, wscale [Cout] receives the per-output-channel scales (largest
+// magnitude of the channel's packed kernel / 448) and the packed values are
+// e4m3(w / wscale); wscale is ignored otherwise.
+hipError_t launch_pack_weights(const float* w, int Cout, int Cin, int prec, int mode, void* dst, float* wscale,
+                               hipStream_t s);
 
 // GroupNorm: merge per-tile partials of each (n, t) frame into per-channel
 // scale/shift for the consumer's prologue.
+// With mr set, also the (mean, rstd) of each (frame, group) for the backward.
 hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const float* gamma,
-                              const float* beta, float eps, float* scale, float* shift,
+                              const float* beta, float eps, float* scale, float* shift, float2* mr,
                               hipStream_t s);
 
 // y = silu(x * scale[n,f,c] + shift[n,f,c]) for f in [0, F): x is frame
@@ -73,6 +126,9 @@ hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const 
 // coincide.  scale/shift are indexed by (n, f).
 hipError_t launch_gn_act(const void* in, int in_Tb, int in_f0, void* out, int out_Tb, int out_f0, int prec, int N,
                          int F, int HW, const float* scale, const float* shift, hipStream_t s);
+// The same from bf16 activations into MX-FP8 activations (out + out_scale).
+hipError_t launch_gn_act_fp8(const void* in, int in_Tb, int in_f0, uint8_t* out, uint8_t* out_scale, int out_Tb,
+                             int out_f0, int N, int F, int HW, const float* scale, const float* shift, hipStream_t s);
 
 struct FsqConst {
   float h[6], o[6], s[6], inv_d[6], d[6];
@@ -104,5 +160,46 @@ hipError_t launch_drop(const DropArgs& d, float* codes, uint8_t* keep, int N, in
 // frames per clip.
 hipError_t launch_proj_in(const float* codes, int N, int T2, int t0, int F, int HW, const float* w,
                           const float* b, int prec, void* out, int out_chunks, int Tb, int f0, hipStream_t s);
+// The same into MX-FP8 activations (128 channels: 2 chunks, 4 scales per position).
+hipError_t launch_proj_in_fp8(const float* codes, int N, int T2, int t0, int F, int HW, const float* w,
+                              const float* b, uint8_t* out, uint8_t* out_scale, int Tb, int f0, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Backward pass (backward.hip).  Dense latent tensors are (N, T2, H2, W2, 6)
+// float; activations and gradients use the chunked layout above.
+// ---------------------------------------------------------------------------
+int l1_blocks(size_t npos);
+int fsq_blocks(size_t ntok);
+size_t outer6_partial_floats(size_t ntok);
+size_t gn_bwd_partial_floats(int frames, int HW, int prec);
+// Partial sums of |x_hat - x| (x uint8, mapped to [-1, 1]) per 256 positions;
+// with g set also the gradient seed gscale * sign(x_hat - x) / numel into a
+// one-chunk activation buffer.  gscale: device scalar or null (1).
+hipError_t launch_l1(const float* xhat, const uint8_t* x, size_t npos, int prec, const float* gscale, void* g,
+                     float* partial, hipStream_t s);
+hipError_t launch_u8_to_chunked(const uint8_t* x, size_t npos, int prec, void* out, hipStream_t s);
+// Commitment partial sums; with gdec set also the straight-through adjoint gz.
+hipError_t launch_fsq_bwd(const float* z, const uint8_t* keep, const float* gdec, size_t ntok, const FsqConst& fc,
+                          float coef, const float* gscale, float* gz, float* partial, hipStream_t s);
+hipError_t launch_loss_final(const float* l1p, int nl1, const float* cp, int nc, float inv_numel, float inv_m,
+                             float commit_weight, float* loss, hipStream_t s);
+// GroupNorm(32) + SiLU backward over `frames` frames of HW positions, 64
+// channels: dx = d/dx of silu(gn(x)) applied to g, plus resid (nullable); dx
+// may alias g or resid.  dgamma / dbeta receive the parameter gradients.
+hipError_t launch_gn_bwd(const void* x, const void* g, const float2* mr, const float* gamma, const float* beta,
+                         const void* resid, void* dx, int frames, int HW, int prec, float* partial, float2* fsum,
+                         float2* m12, float* dgamma, float* dbeta, hipStream_t s);
+// fine[n, 2t, 2h, 2w] = coarse[n, t, h, w], zero elsewhere (adjoint of a stride-2 subsampling).
+hipError_t launch_zero_insert(const void* coarse, void* fine, int N, int Tf, int Hf, int Wf, int chunks, int prec,
+                              hipStream_t s);
+// Adjoint of the nearest x2 upsample (time map t -> ceil(t / 2)).
+hipError_t launch_up_adjoint(const void* fine, void* coarse, int N, int Tc, int Hc, int Wc, int chunks, int prec,
+                             hipStream_t s);
+// y[p][k] = sum_c w6[k][c] x[p][c] (128 chunked channels -> 6 dense).
+hipError_t launch_proj6(const void* x, size_t ntok, int HW, const float* w6, float* y, int prec, hipStream_t s);
+// 1x1x1 weight / bias gradients from dense a6 (6 wide) and chunked x (128).
+hipError_t launch_outer6(const float* a6, const void* x, size_t ntok, int HW, int prec, float* partial,
+                         int transposed, float* dw, float* db, hipStream_t s);
+hipError_t launch_transpose(const float* in, int R, int C, float* out, hipStream_t s);
 
 }  // namespace tok

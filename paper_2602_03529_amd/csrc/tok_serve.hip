@@ -343,6 +343,9 @@ tok_status tok_server_request_bytes(const tok_model* model, int T, int H, int W,
 
 tok_status tok_server_create(tok_model* model, size_t budget_bytes, int slots, int max_batch, tok_server** out) {
   if (!model || !out || slots < 1 || max_batch < 1 || budget_bytes < 4096) return TOK_EINVAL;
+  size_t probe = 0;  // the server runs round trips: the model must support them
+  const tok_status ps = tok_workspace_size(model, 1, 1, 4, 4, TOK_WS_ROUNDTRIP, &probe);
+  if (ps != TOK_OK) return ps;
   tok_server* sv = new tok_server;
   sv->model = model;
   sv->max_batch = max_batch;

@@ -120,13 +120,95 @@ class TokModel:
         T, H, W = 4 * (T2 - 1) + 1, 4 * H2, 4 * W2
         xh = out if out is not None else torch.empty((N, T, H, W, 3), dtype=torch.float32, device=codes.device)
         if ws is None:
-            ws = self.workspace(N, T, H, W)
+            ws = self.workspace(N, T, H, W, L.TOK_WS_DECODE if self.precision == "fp8" else L.TOK_WS_ROUNDTRIP)
         L.check("tok_decode", self.lib.tok_decode(self.handle, _ptr(codes), N, T2, H2, W2, _ptr(xh), _ptr(ws),
                                                   ws.numel(), _stream(codes.device)))
         return xh
 
 
-KERNEL_IDS = 18
+    # ---- training step (tok_train_forward / tok_backward) -----------------
+    def set_weights(self, w: torch.Tensor):
+        """Replace the parameters by a device float32 blob (canonical order) and repack."""
+        _need(w, torch.float32, (weight_count(),), "weights")
+        L.check("tok_model_set_weights", self.lib.tok_model_set_weights(self.handle, _ptr(w), _stream(w.device)))
+
+    def train_workspace_size(self, N, T, H, W) -> int:
+        n = C.c_size_t()
+        L.check("tok_train_workspace_size", self.lib.tok_train_workspace_size(self.handle, N, T, H, W, C.byref(n)))
+        return int(n.value)
+
+    def train_forward(self, x: torch.Tensor, keep: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                      xhat=False, z=False, idx=False):
+        """Loss of the training objective on uint8 clips x (N,T,H,W,3).  Returns
+        dict(loss=float32 (3,) {L, l1 term, commitment mean}, ws=the workspace
+        holding the tape, and the requested optional outputs)."""
+        N, T, H, W, _ = x.shape
+        _need(x, torch.uint8, (N, T, H, W, 3), "x")
+        T2, H2, W2 = latent_shape(T, H, W)
+        dev = x.device
+        if keep is not None:
+            _need(keep, torch.uint8, (N, T2, H2, W2), "keep")
+        if ws is None:
+            ws = torch.empty(self.train_workspace_size(N, T, H, W), dtype=torch.uint8, device=dev)
+        loss = torch.empty(3, dtype=torch.float32, device=dev)
+        out = dict(loss=loss, ws=ws)
+        out["xhat"] = torch.empty((N, T, H, W, 3), dtype=torch.float32, device=dev) if xhat else None
+        out["z"] = torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=dev) if z else None
+        out["idx"] = torch.empty((N, T2, H2, W2), dtype=torch.int32, device=dev) if idx else None
+        L.check("tok_train_forward", self.lib.tok_train_forward(
+            self.handle, _ptr(x), N, T, H, W, _ptr(keep), _ptr(loss), _ptr(out["xhat"]), _ptr(out["z"]),
+            _ptr(out["idx"]), _ptr(ws), ws.numel(), _stream(dev)))
+        return out
+
+    def backward(self, x: torch.Tensor, ws: torch.Tensor, gloss: torch.Tensor | None = None,
+                 dweights: torch.Tensor | None = None, dx=False):
+        """Gradients of the last train_forward on (x, ws): dict(dweights, dx)."""
+        N, T, H, W, _ = x.shape
+        _need(x, torch.uint8, (N, T, H, W, 3), "x")
+        dev = x.device
+        if gloss is not None:
+            _need(gloss, torch.float32, (1,), "gloss")
+        if dweights is None:
+            dweights = torch.empty(weight_count(), dtype=torch.float32, device=dev)
+        dxt = torch.empty((N, T, H, W, 3), dtype=torch.float32, device=dev) if dx else None
+        L.check("tok_backward", self.lib.tok_backward(
+            self.handle, _ptr(x), N, T, H, W, _ptr(gloss), _ptr(dweights), _ptr(dxt), _ptr(ws), ws.numel(),
+            _stream(dev)))
+        return dict(dweights=dweights, dx=dxt)
+
+
+class TokenizerLoss(torch.autograd.Function):
+    """L(params) of the training objective with the library's hand-written
+    backward: forward runs tok_train_forward (after loading `params` into the
+    model when they changed), backward runs tok_backward with the incoming
+    gradient as its scale.  Each call keeps its own tape (workspace) until its
+    backward has run."""
+
+    @staticmethod
+    def forward(ctx, params, model, x, keep):
+        key = (params.data_ptr(), params._version)
+        if getattr(model, "_params_key", None) != key:
+            model.set_weights(params.detach())
+            model._params_key = key
+        out = model.train_forward(x, keep)
+        ctx.model, ctx.x, ctx.ws = model, x, out["ws"]
+        model.last_loss = out["loss"]
+        return out["loss"][0].clone()
+
+    @staticmethod
+    def backward(ctx, gout):
+        g = gout.detach().reshape(1).to(torch.float32).contiguous()
+        res = ctx.model.backward(ctx.x, ctx.ws, gloss=g)
+        ctx.ws = None
+        return res["dweights"], None, None, None
+
+
+def tokenizer_loss(model: "TokModel", params: torch.Tensor, x: torch.Tensor, keep: torch.Tensor | None = None):
+    """Differentiable training loss; params: float32 (weight_count(),) cuda tensor."""
+    return TokenizerLoss.apply(params, model, x, keep)
+
+
+KERNEL_IDS = 22
 
 
 class Profile:
