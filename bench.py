@@ -114,6 +114,75 @@ def train_leg(tok, synth, wflat, dev, args):
     return out
 
 
+FP8_PEAK_TFLOPS = 5000.0
+PEAKS = {"fp8": FP8_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS, "f32": F32_PEAK_TFLOPS}
+DECODE_CONVS = ["dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a", "dec.rb2.b", "dec.conv_out"]
+
+
+def synthetic_codes(N, T2, H2, W2, dev, seed=11):
+    """Uniformly drawn valid FSQ codes (levels 8,8,8,5,5,5) of the latent shape."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    lv = torch.tensor([8, 8, 8, 5, 5, 5])
+    half = torch.div(lv, 2, rounding_mode="floor")
+    u = torch.rand((N, T2, H2, W2, 6), generator=g)
+    q = torch.floor(u * lv).to(torch.int64) - half
+    return (q.to(torch.float32) / half.to(torch.float32)).contiguous().to(dev)
+
+
+def fp8_leg(tok, wflat, dev, args):
+    """Decode-only comparison of the fp8, bf16 and f32 decoders at the fp8 workload."""
+    import torch
+    N, T, H, W = (int(v) for v in args.fp8_shape.split("x"))
+    T2, H2, W2 = (T - 1) // 4 + 1, H // 4, W // 4
+    codes = synthetic_codes(N, T2, H2, W2, dev)
+    pos = level_positions(N, T, H, W)
+    out = dict(workload="decode only, %d clips x %d frames x %dx%d, synthetic uniform FSQ codes" % (N, T, W, H),
+               batch=N, frames=T, height=H, width=W, realtime_budget_fps=30)
+    for prec, steps in (("fp8", args.fp8_steps), ("bf16", args.fp8_steps), ("f32", 1)):
+        m = tok.TokModel(wflat, prec)
+        ws = torch.empty(m.workspace_size(N, T, H, W, what=2), dtype=torch.uint8, device=dev)
+        xh = torch.empty((N, T, H, W, 3), dtype=torch.float32, device=dev)
+        m.decode(codes, out=xh, ws=ws)
+        torch.cuda.synchronize()
+        prof = tok.Profile(m)
+        prof.__enter__()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            m.decode(codes, out=xh, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        prof.__exit__(None, None, None)
+        ms = e0.elapsed_time(e1) / steps
+        conv = {}
+        for k in DECODE_CONVS:
+            c = prof.count[k]
+            if c:
+                t = prof.ms[k] / c
+                f = CONV_FLOPS[k][0] * pos[CONV_FLOPS[k][1]]
+                conv[k] = dict(avg_ms=round(t, 3), tflops=round(f / (t / 1e3) / 1e12, 1),
+                               frac_of_peak=round(f / (t / 1e3) / 1e12 / PEAKS[prec], 3))
+        rb = [conv[k] for k in DECODE_CONVS if ".rb" in k and k in conv]
+        gn = prof.ms["gn_silu"] / max(prof.count["gn_silu"], 1)
+        # GN+SiLU pass: bf16 in (128 B / position), out bf16 (128 B) or MX-FP8 (64 B + 2 B scales)
+        gn_bytes = pos[0] * (128 + (66 if prec == "fp8" else (128 if prec == "bf16" else 0)))
+        if prec == "f32":
+            gn_bytes = pos[0] * 512
+        out[prec] = dict(ms_per_step=round(ms, 2), frames_per_s=round(N * T / (ms / 1e3), 2),
+                         realtime_streams_at_30fps=round(N * T / (ms / 1e3) / 30.0, 2),
+                         rb_conv_frac_of_peak=round(sum(r["frac_of_peak"] for r in rb) / max(len(rb), 1), 3),
+                         peak_tflops=PEAKS[prec], convs=conv,
+                         gn_silu_avg_ms=round(gn, 3), gn_silu_gbps=round(gn_bytes / (gn / 1e3) / 1e9, 1))
+        print("bench: decode %s %.2f ms/step" % (prec, ms), file=sys.stderr, flush=True)
+        del ws, xh
+        m.close()
+        torch.cuda.empty_cache()
+    out["fp8_speedup_vs_bf16"] = round(out["bf16"]["ms_per_step"] / out["fp8"]["ms_per_step"], 3)
+    out["fp8_speedup_vs_f32"] = round(out["f32"]["ms_per_step"] / out["fp8"]["ms_per_step"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +198,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=3,
                     help="timed training steps (forward + backward) per precision; 0 skips the training leg")
     ap.add_argument("--train-shape", type=str, default="8x17x256x256", help="NxTxHxW of the training batch")
+    ap.add_argument("--fp8-steps", type=int, default=3,
+                    help="timed decode steps of the fp8 leg (bf16 the same, f32 one); 0 skips it")
+    ap.add_argument("--fp8-shape", type=str, default="2x33x1080x1920", help="NxTxHxW of the decode-only fp8 leg")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -247,6 +319,11 @@ def main():
     if args.train_steps > 0:
         train = train_leg(tok, synth, wflat, dev, args)
 
+    # ---- fp8 decoder (decode-only workload), vs bf16 and f32 ---------------
+    fp8 = None
+    if args.fp8_steps > 0:
+        fp8 = fp8_leg(tok, wflat, dev, args)
+
     # ---- CPU oracle on a bounded sample + PSNR criterion on that sample ----
     cpu = None
     psnr = None
@@ -275,6 +352,17 @@ def main():
                     idx_agreement=round(float((out["idx"].cpu().numpy() == ref["idx"]).mean()), 4))
         psnr["criterion_abs_diff_db"] = round(abs(psnr["gpu_bf16_vs_source_db"] - psnr["oracle_vs_source_db"]), 4)
         psnr["pass"] = bool(psnr["criterion_abs_diff_db"] <= 0.5)
+        # decoders of every precision on the oracle's own codes of the same crop
+        oc = torch.from_numpy(np.ascontiguousarray(ref["dec_in"], np.float32)).to(dev)
+        dec = {}
+        for prec in ("f32", "bf16", "fp8"):
+            md = mb if prec == "bf16" else tok.TokModel(wflat, prec)
+            xd = md.decode(oc).cpu().numpy()
+            dec[prec] = dict(psnr_vs_oracle_db=round(O.psnr(xd, ref["xhat"]), 3),
+                             max_abs_err=float(np.abs(xd - ref["xhat"]).max()))
+            if md is not mb:
+                md.close()
+        psnr["decode_of_oracle_codes"] = dec
 
     line = dict(metric=METRIC, value=round(value, 3), unit="frames/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(ms_b, 3), higher_is_better=True, scaling="weak",
@@ -284,7 +372,8 @@ def main():
                             batch=N, frames=T, height=H, width=W, precision="bf16"),
                 algorithmic_tflops_per_step=round(total_flops / 1e12, 3),
                 achieved_tflops=round(total_flops / (ms_b / 1e3) / 1e12, 2),
-                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, train=train, per_kernel=per_kernel)
+                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, train=train, fp8=fp8,
+                per_kernel=per_kernel)
     print(json.dumps(line), flush=True)
 
 

@@ -209,6 +209,25 @@ tok_status tok_backward(tok_model* model, const uint8_t* x, int N, int T, int H,
                         const float* gloss, float* dweights, float* dx, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* Weight and bias gradient of one causal 3x3x3 convolution, the building
+ * block tok_backward uses for every 3x3x3 layer:
+ *   dw[o][i][kt][kh][kw] = sum over output positions p of dy[p][o] * x~[p + tap][i]
+ *   db[o]                = sum over p of dy[p][o]
+ * where x~ is the conv's input as the tap reads it (causal time clamp, zero
+ * outside the frame).  view 0: stride 1 (To = Ti, Ho = Hi, Wo = Wi); view 1:
+ * stride 2 (To = (Ti-1)/2+1, Ho = Hi/2, Wo = Wi/2); view 2: nearest x2
+ * upsampled input (To = 2 Ti - 1, Ho = 2 Hi, Wo = 2 Wi).  x (N,Ti,Hi,Wi,Cin)
+ * and dy (N,To,Ho,Wo,Cout) are device tensors of `prec` (TOK_F32 or
+ * TOK_BF16) in the library's chunked activation layout
+ * [N][T][ceil(C/CH)][H][W][CH], CH = 64 bytes / element size, channels past
+ * C zero.  dw: float32 (Cout,Cin,3,3,3), db: float32 (Cout) or NULL.  Results
+ * are deterministic (fixed-order reduction of per-split partials in ws). */
+tok_status tok_conv3d_wgrad_workspace_size(tok_precision prec, int view, int N, int To, int Ho, int Wo, int Cin,
+                                           int Cout, size_t* bytes);
+tok_status tok_conv3d_wgrad(tok_precision prec, int view, const void* x, int N, int Ti, int Hi, int Wi, int Cin,
+                            const void* dy, int To, int Ho, int Wo, int Cout, float* dw, float* db, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Streaming request loop (continuous batching under an HBM budget).
  *

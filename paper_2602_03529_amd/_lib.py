@@ -75,6 +75,10 @@ def lib():
     L.tok_train_forward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.tok_backward.restype = i32
     L.tok_backward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+    L.tok_conv3d_wgrad_workspace_size.restype = i32
+    L.tok_conv3d_wgrad_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_conv3d_wgrad.restype = i32
+    L.tok_conv3d_wgrad.argtypes = [i32, i32, vp, i32, i32, i32, i32, i32, vp, i32, i32, i32, i32, vp, vp, vp, sz, vp]
     L.tok_profile_begin.restype = i32
     L.tok_profile_begin.argtypes = [vp]
     L.tok_profile_end.restype = i32

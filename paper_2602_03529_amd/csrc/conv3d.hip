@@ -71,11 +71,22 @@ template <> struct Geo<CM_UPF> {
   static constexpr int MB = (TH / 2) * (TW / 2 / 16), WT = 16, KTS = 2;
 };
 
+// Stride-1 modes give each wave a 4 x 32 sub-tile (waves 2 x 2 over the 8 x 64
+// workgroup tile): an activation operand loaded for halo row r then serves
+// output rows r - kh for every kh, a third fewer LDS reads than 2 x 64 rows.
+#ifndef TOK_S1_TALL
+#define TOK_S1_TALL 1
+#endif
+constexpr bool kS1Tall = TOK_S1_TALL != 0;
+
 // Output-tile-local position of lane l16 in position block m of a wave.
 template <int MODE>
 __device__ __forceinline__ void out_local(int wave, int m, int l16, int* i, int* j) {
   using G = Geo<MODE>;
-  if constexpr (MODE == CM_UPF) {
+  if constexpr ((MODE == CM_S1 || MODE == CM_S1T) && kS1Tall) {
+    *i = 4 * (wave >> 1) + (m >> 1);
+    *j = 32 * (wave & 1) + 16 * (m & 1) + l16;
+  } else if constexpr (MODE == CM_UPF) {
     *i = 2 * (m >> 1) + (wave >> 1);
     *j = 2 * ((m & 1) * 16 + l16) + (wave & 1);
   } else {
@@ -364,7 +375,6 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
           }
         }
       } else {
-        constexpr int BPR = G::TW / 16;
 #pragma unroll 1
         for (int pr = 0; pr < 5; ++pr) {
           const int tp = 2 * pr + (g4 >> 1);
@@ -379,8 +389,8 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
           }
 #pragma unroll
           for (int m = 0; m < MB; ++m) {
-            const int i = wave * G::WR + m / BPR;
-            const int j = (m % BPR) * 16 + l16;
+            int i, j;
+            out_local<MODE>(wave, m, l16, &i, &j);
             const int row = act_row<MODE>(i, j, kh, kw);
             const i32x8 aq = ld_fp8_half(lds_a[buf], row, hb);
             const int sb = (lds_sc[row] >> (8 * hb)) & 255;
@@ -408,6 +418,37 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
           const uint4 aq = lds_a[buf][row * 4 + (g4 ^ swz(row))];
 #pragma unroll
           for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
+        }
+      }
+      return;
+    }
+    if constexpr ((MODE == CM_S1 || MODE == CM_S1T) && kS1Tall) {
+      // per kw: the 6 halo rows x 2 column blocks this wave reads, reused for kh = 0, 1, 2
+      static_assert(MB == 8, "4 x 32 wave tile");
+      const int i0 = 4 * (wave >> 1), j0 = 32 * (wave & 1) + l16;
+#pragma unroll 1
+      for (int kw = 0; kw < 3; ++kw) {
+        uint4 bq[6][2];
+#pragma unroll
+        for (int hr = 0; hr < 6; ++hr)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            const int row = (i0 + hr) * G::HW + j0 + 16 * cb + kw;
+            bq[hr][cb] = lds_a[buf][row * 4 + (g4 ^ swz(row))];
+          }
+#pragma unroll
+        for (int kh = 0; kh < 3; ++kh) {
+          uint4 wq[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int row = (kh * 3 + kw) * NT + b * 16 + l16;
+            wq[b] = lds_w[buf][row * 4 + (g4 ^ swz(row))];
+          }
+#pragma unroll
+          for (int m = 0; m < MB; ++m) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], bq[(m >> 1) + kh][m & 1]);
+          }
         }
       }
       return;
@@ -836,6 +877,192 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradLaunch a) {
   if (bias_sum && tid < 64 && ot * 64 + tid < a.Cout) a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = bsum;
 }
 
+// ---------------------------------------------------------------------------
+// Weight gradient on bf16 MFMA (bf16 operands, Cin and Cout multiples of 64).
+// D[o][i] += dy[p][o] x~[p + tap][i] with K = output positions: 16x16x32 bf16
+// MFMAs, A = dy (rows o), B = x (columns i).  Block = (temporal tap, 64
+// output channels, 64 input channels, split); wave w owns input channels
+// 16w .. 16w+15 and all 64 output channels x 9 spatial taps (36 accumulator
+// blocks).  An item is TH output rows x 64 columns of one output frame.  Both
+// operands need K (positions) contiguous in LDS, so dy and the input halo are
+// transposed while staged (8 x 8 register transposes, 16-byte LDS stores):
+//   s_dy[o][p], p = r * 64 + c;   s_x[i][row][plane][col]
+// with rows / columns of the conv's input as the tap sees it: stride 1 and
+// the upsampled view store the (upsampled) halo directly; stride 2 stores the
+// halo's even and odd columns in two planes.  The column read by tap kw is
+// then offset by 0, 1 or 2 elements from a 16-byte boundary; offset reads
+// take 5 dwords and realign them with byte shifts.
+// ---------------------------------------------------------------------------
+template <int VIEW> struct WMGeo;
+template <> struct WMGeo<CM_S1> { static constexpr int TH = 2, ROWS = 4, PLANES = 1; };
+template <> struct WMGeo<CM_UP> { static constexpr int TH = 2, ROWS = 4, PLANES = 1; };
+template <> struct WMGeo<CM_S2> { static constexpr int TH = 1, ROWS = 3, PLANES = 2; };
+constexpr int kWmCols = 72;   // halo columns per plane row (>= 66, multiple of 8)
+
+template <int VIEW> struct WMLds {
+  using G = WMGeo<VIEW>;
+  static constexpr int NPOS = G::TH * 64;
+  static constexpr int DYS = NPOS + 8;  // s_dy row stride (elements): 4 dwords mod 32 banks
+  static constexpr int XR = G::ROWS * G::PLANES * kWmCols;
+  static constexpr int XS = ((XR / 2 + 27) / 32) * 32 * 2 + 8;  // s_x channel stride: 4 dwords mod 32 banks
+};
+
+// 8 x 8 transpose of bf16: v[p] holds 8 channels of position p; w[c] receives
+// 8 positions of channel c.
+__device__ __forceinline__ void transpose8x8_bf16(const uint4* v, uint4* w) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    uint32_t d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a = (&v[2 * j].x)[c >> 1], b = (&v[2 * j + 1].x)[c >> 1];
+      d[j] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+    }
+    w[c] = make_uint4(d[0], d[1], d[2], d[3]);
+  }
+}
+
+// 8 bf16 at element offset e0 + mis (e0 a multiple of 8) of an LDS array.
+__device__ __forceinline__ uint4 ld8_bf16(const uint16_t* base, int e0, int mis) {
+  const uint32_t* d = reinterpret_cast<const uint32_t*>(base + e0);
+  if (mis == 0) return *reinterpret_cast<const uint4*>(d);
+  if (mis == 2) return make_uint4(d[1], d[2], d[3], d[4]);
+  const uint32_t w0 = d[0], w1 = d[1], w2 = d[2], w3 = d[3], w4 = d[4];
+  return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2), __builtin_amdgcn_alignbyte(w2, w1, 2),
+                    __builtin_amdgcn_alignbyte(w3, w2, 2), __builtin_amdgcn_alignbyte(w4, w3, 2));
+}
+
+template <int VIEW>
+__global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
+  using G = WMGeo<VIEW>;
+  using Lp = WMLds<VIEW>;
+  constexpr int NPOS = Lp::NPOS, KS = NPOS / 32;
+  __shared__ __align__(16) uint16_t s_dy[64 * Lp::DYS];
+  __shared__ __align__(16) uint16_t s_x[64 * Lp::XS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int ic_tiles = a.Cin / 64, oc_tiles = a.Cout / 64;
+  int v = blockIdx.x;
+  const int sp = v % a.splits; v /= a.splits;
+  const int ot = v % oc_tiles; v /= oc_tiles;
+  const int it = v % ic_tiles; v /= ic_tiles;
+  const int kt = v;
+  const int tiles_h = (a.Ho + G::TH - 1) / G::TH, tiles_w = (a.Wo + 63) / 64;
+  const long long items = (long long)a.N * a.To * tiles_h * tiles_w;
+  const long long i0 = items * sp / a.splits, i1 = items * (sp + 1) / a.splits;
+  const bool bias_sum = a.bpartial && kt == 0 && it == 0;
+  float bsum = 0.f;
+
+  f32x4 acc[4][9];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[b][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const size_t plane_x = (size_t)a.Hi * a.Wi, plane_y = (size_t)a.Ho * a.Wo;
+  const uint4* dyq = reinterpret_cast<const uint4*>(a.dy);
+  const uint4* xq = reinterpret_cast<const uint4*>(a.x);
+  for (long long item = i0; item < i1; ++item) {
+    long long u = item;
+    const int tw = (int)(u % tiles_w); u /= tiles_w;
+    const int th = (int)(u % tiles_h); u /= tiles_h;
+    const int to = (int)(u % a.To); u /= a.To;
+    const int n = (int)u;
+    const int h0 = th * G::TH, w0 = tw * 64;
+    int ts;
+    if constexpr (VIEW == CM_S1) ts = max(to + kt - 2, 0);
+    else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
+    else ts = (max(to + kt - 2, 0) + 1) >> 1;
+    __syncthreads();
+    // ---- stage dy: blocks of 8 positions x 8 output channels ----
+    for (int blk = tid; blk < (NPOS / 8) * 8; blk += 256) {
+      const int pb = blk >> 3, cb = blk & 7;
+      uint4 vv[8], ww[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int p = pb * 8 + k;
+        const int oh = h0 + p / 64, ow = w0 + p % 64;
+        const int oc = ot * 64 + cb * 8;  // 8 channels inside one 32-channel chunk
+        vv[k] = make_uint4(0, 0, 0, 0);
+        if (oh < a.Ho && ow < a.Wo)
+          vv[k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + oc / 32) * plane_y + (size_t)oh * a.Wo + ow) * 4 +
+                      (oc % 32) / 8];
+      }
+      transpose8x8_bf16(vv, ww);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) *reinterpret_cast<uint4*>(&s_dy[(cb * 8 + k) * Lp::DYS + pb * 8]) = ww[k];
+    }
+    // ---- stage the input halo: blocks of 8 columns (of one plane row) x 8 input channels ----
+    constexpr int QB = kWmCols / 8;
+    for (int blk = tid; blk < G::ROWS * G::PLANES * QB * 8; blk += 256) {
+      int r = blk;
+      const int cb = r % 8; r /= 8;
+      const int qb = r % QB; r /= QB;
+      const int pl = r % G::PLANES; r /= G::PLANES;
+      const int hr = r;
+      uint4 vv[8], ww[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int q = qb * 8 + k;
+        int hs, ws;
+        if constexpr (VIEW == CM_S1) { hs = h0 - 1 + hr; ws = w0 - 1 + q; }
+        else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + hr; ws = 2 * w0 - 1 + 2 * q + pl; }
+        else {  // upsampled coordinates -> source
+          const int hu = h0 - 1 + hr, wu = w0 - 1 + q;
+          hs = hu < 0 ? -1 : hu >> 1;
+          ws = wu < 0 ? -1 : wu >> 1;
+        }
+        const int ic = it * 64 + cb * 8;
+        vv[k] = make_uint4(0, 0, 0, 0);
+        if (q < 66 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi)
+          vv[k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ic / 32) * plane_x + (size_t)hs * a.Wi + ws) * 4 +
+                     (ic % 32) / 8];
+      }
+      transpose8x8_bf16(vv, ww);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        *reinterpret_cast<uint4*>(&s_x[(cb * 8 + k) * Lp::XS + (hr * G::PLANES + pl) * kWmCols + qb * 8]) = ww[k];
+    }
+    __syncthreads();
+    if (bias_sum && tid < 64) {
+      for (int p = 0; p < NPOS; ++p) bsum += __uint_as_float((uint32_t)s_dy[tid * Lp::DYS + p] << 16);
+    }
+    // ---- K loop over the item's positions, 32 per step ----
+    const uint16_t* xrow = s_x + (wave * 16 + l16) * Lp::XS;
+#pragma unroll 1
+    for (int ks = 0; ks < KS; ++ks) {
+      const int pr = (ks * 32) / 64, pc = (ks * 32) % 64 + 8 * g4;  // this lane's 8 positions: row pr, cols pc..pc+7
+      bf16x8 av[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        av[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_dy[(b * 16 + l16) * Lp::DYS + ks * 32 + 8 * g4]));
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int kh = t / 3, kw = t % 3;
+        int row, pl, col, mis;
+        if constexpr (VIEW == CM_S2) { row = 2 * pr + kh; pl = kw & 1; col = pc; mis = kw >> 1; }
+        else { row = pr + kh; pl = 0; col = pc; mis = kw; }
+        const uint4 xv = ld8_bf16(xrow, (row * G::PLANES + pl) * kWmCols + col, mis);
+        const bf16x8 bv = __builtin_bit_cast(bf16x8, xv);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b], bv, acc[b][t], 0, 0, 0);
+      }
+    }
+  }
+  // D block (o, i): lane holds o = 16 b + 4 g4 + r, i = 16 wave + l16
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int oc = ot * 64 + b * 16 + 4 * g4 + r, icn = it * 64 + wave * 16 + l16;
+        a.partial[((((size_t)sp * 3 + kt) * 9 + t) * a.Cout + oc) * a.Cin + icn] = acc[b][t][r];
+      }
+  if (bias_sum && tid < 64) a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = bsum;
+}
+
 // Sums the per-split partials in split order: weights into the canonical
 // [o][i][kt][kh][kw] layout, then (elements past the weights) the bias.
 __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ partial,
@@ -903,17 +1130,40 @@ hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-int wgrad_items(int view, int N, int To, int Ho, int Wo) {
+namespace {
+bool wgrad_uses_mfma_bf16(int prec, int Cout, int Cin) { return prec == P_BF16 && Cin % 64 == 0 && Cout % 64 == 0; }
+}  // namespace
+
+int wgrad_blocks_per_split(int prec, int view, int Cout, int Cin) {
+  (void)view;
+  if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) return 3 * (Cin / 64) * (Cout / 64);
+  return 3 * ((Cin + 31) / 32) * ((Cout + 63) / 64);
+}
+
+int wgrad_items(int prec, int view, int Cout, int Cin, int N, int To, int Ho, int Wo) {
   int th, tw;
-  if (view == CM_S2) { th = WGeo<CM_S2>::TH; tw = WGeo<CM_S2>::TW; }
-  else { th = WGeo<CM_S1>::TH; tw = WGeo<CM_S1>::TW; }
+  if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) {
+    th = view == CM_S2 ? WMGeo<CM_S2>::TH : WMGeo<CM_S1>::TH;
+    tw = 64;
+  } else if (view == CM_S2) {
+    th = WGeo<CM_S2>::TH; tw = WGeo<CM_S2>::TW;
+  } else {
+    th = WGeo<CM_S1>::TH; tw = WGeo<CM_S1>::TW;
+  }
   return N * To * ((Ho + th - 1) / th) * ((Wo + tw - 1) / tw);
 }
 
 hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s) {
-  const long long nb = 3LL * ((a.Cin + 31) / 32) * ((a.Cout + 63) / 64) * a.splits;
+  const long long nb = (long long)wgrad_blocks_per_split(a.prec, a.view, a.Cout, a.Cin) * a.splits;
   if (nb <= 0 || nb > 0x7fffffffLL || a.splits < 1) return hipErrorInvalidValue;
   const dim3 g((unsigned)nb), b(256);
+  if (wgrad_uses_mfma_bf16(a.prec, a.Cout, a.Cin)) {
+    if (a.view == CM_S1) hipLaunchKernelGGL(wgrad_mfma_kernel<CM_S1>, g, b, 0, s, a);
+    else if (a.view == CM_S2) hipLaunchKernelGGL(wgrad_mfma_kernel<CM_S2>, g, b, 0, s, a);
+    else if (a.view == CM_UP) hipLaunchKernelGGL(wgrad_mfma_kernel<CM_UP>, g, b, 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
 #define TOK_WG(P, V) hipLaunchKernelGGL((wgrad_kernel<P, V>), g, b, 0, s, a)
   if (a.prec == P_BF16) {
     if (a.view == CM_S1) TOK_WG(P_BF16, CM_S1);

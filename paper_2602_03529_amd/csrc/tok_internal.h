@@ -56,7 +56,11 @@ struct WgradLaunch {
   float* partial;     // [splits][3][9][Cout][Cin]
   float* bpartial;    // [splits][Cout] or null
 };
-int wgrad_items(int view, int N, int To, int Ho, int Wo);
+// Blocks per split, and work items (output tiles) shared among the splits,
+// of the weight-gradient launch for these operands: bf16 operands with Cin
+// and Cout multiples of 64 run on bf16 MFMA, everything else on fp32 MFMA.
+int wgrad_blocks_per_split(int prec, int view, int Cout, int Cin);
+int wgrad_items(int prec, int view, int Cout, int Cin, int N, int To, int Ho, int Wo);
 hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s);
 hipError_t launch_wgrad_reduce(const float* partial, const float* bpartial, int splits, int Cout, int Cin, float* dw,
                                float* db, hipStream_t s);

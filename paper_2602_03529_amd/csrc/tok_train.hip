@@ -46,10 +46,10 @@ struct TrainPlan {
 
 struct WgradShape { int layer, view, Ti, Hi, Wi, To, Ho, Wo; };
 
-int wgrad_splits(int view, int Cout, int Cin, int N, int To, int Ho, int Wo) {
-  const int per = 3 * cdiv(Cin, 32) * cdiv(Cout, 64);
-  const int items = wgrad_items(view, N, To, Ho, Wo);
-  return std::max(1, std::min(items, kWgradTargetBlocks / per));
+int wgrad_splits(int prec, int view, int Cout, int Cin, int N, int To, int Ho, int Wo) {
+  const int per = wgrad_blocks_per_split(prec, view, Cout, Cin);
+  const int items = wgrad_items(prec, view, Cout, Cin, N, To, Ho, Wo);
+  return std::max(1, std::min(items, std::max(1, kWgradTargetBlocks / per)));
 }
 
 std::vector<WgradShape> wgrad_shapes(const Dims& d) {
@@ -92,7 +92,7 @@ TrainPlan make_train_plan(const Dims& d, int prec) {
   size_t wp = 0, wbp = 0;
   for (const WgradShape& w : wgrad_shapes(d)) {
     const ConvSpec& c = kConv[w.layer];
-    const size_t sp = wgrad_splits(w.view, c.cout, c.cin, d.N, w.To, w.Ho, w.Wo);
+    const size_t sp = wgrad_splits(prec, w.view, c.cout, c.cin, d.N, w.To, w.Ho, w.Wo);
     wp = std::max(wp, sp * 27 * c.cout * c.cin);
     wbp = std::max(wbp, sp * c.cout);
   }
@@ -175,7 +175,7 @@ tok_status wgrad(const TrainCtx& c, int l, int view, const void* x, int Ti, int 
   a.x = x; a.N = c.p.d.N; a.Ti = Ti; a.Hi = Hi; a.Wi = Wi; a.x_chunks = cdiv(cs.cin, c.CH);
   a.dy = dy; a.To = To; a.Ho = Ho; a.Wo = Wo; a.dy_chunks = cdiv(cs.cout, c.CH);
   a.Cout = cs.cout; a.Cin = cs.cin; a.view = view; a.prec = c.m->prec;
-  a.splits = wgrad_splits(view, cs.cout, cs.cin, c.p.d.N, To, Ho, Wo);
+  a.splits = wgrad_splits(c.m->prec, view, cs.cout, cs.cin, c.p.d.N, To, Ho, Wo);
   a.partial = c.at<float>(c.p.WP);
   a.bpartial = c.at<float>(c.p.WBP);
   Timed tm(c.m, K_WGRAD, c.s);
@@ -409,6 +409,55 @@ tok_status tok_backward(tok_model* m, const uint8_t* x, int N, int T, int H, int
   }
   TOK_TRY(wgrad(c, L_CONV_IN, CM_S1, c.at(p.GX), T, H, W, GB, T, H, W, dweights));
   if (dx) TOK_TRY(adj(c, L_CONV_IN, GB, T, H, W, dx, OUT_RGB32));
+  return TOK_OK;
+}
+
+namespace {
+bool wgrad_op_shape(int view, int N, int Ti, int Hi, int Wi, int To, int Ho, int Wo) {
+  if (N < 1 || Ti < 1 || Hi < 1 || Wi < 1) return false;
+  if (view == CM_S1) return To == Ti && Ho == Hi && Wo == Wi;
+  if (view == CM_S2) return Ti % 2 == 1 && Hi % 2 == 0 && Wi % 2 == 0 && To == (Ti - 1) / 2 + 1 && Ho == Hi / 2 &&
+                            Wo == Wi / 2;
+  if (view == CM_UP) return To == 2 * Ti - 1 && Ho == 2 * Hi && Wo == 2 * Wi;
+  return false;
+}
+int view_mode(int view) { return view == 0 ? CM_S1 : (view == 1 ? CM_S2 : (view == 2 ? CM_UP : -1)); }
+size_t wgrad_op_bytes(int P, int mode, int N, int To, int Ho, int Wo, int Cin, int Cout, int* splits) {
+  *splits = wgrad_splits(P, mode, Cout, Cin, N, To, Ho, Wo);
+  return align256((size_t)*splits * 27 * Cout * Cin * 4) + align256((size_t)*splits * Cout * 4);
+}
+}  // namespace
+
+tok_status tok_conv3d_wgrad_workspace_size(tok_precision prec, int view, int N, int To, int Ho, int Wo, int Cin,
+                                           int Cout, size_t* bytes) {
+  if (!bytes || (prec != TOK_F32 && prec != TOK_BF16) || view_mode(view) < 0 || Cin < 1 || Cout < 1)
+    return fail(TOK_EINVAL, "bad argument");
+  int sp;
+  *bytes = wgrad_op_bytes(prec == TOK_BF16 ? P_BF16 : P_F32, view_mode(view), N, To, Ho, Wo, Cin, Cout, &sp);
+  return TOK_OK;
+}
+
+tok_status tok_conv3d_wgrad(tok_precision prec, int view, const void* x, int N, int Ti, int Hi, int Wi, int Cin,
+                            const void* dy, int To, int Ho, int Wo, int Cout, float* dw, float* db, void* ws,
+                            size_t ws_bytes, hipStream_t s) {
+  if (!x || !dy || !dw || !ws || (prec != TOK_F32 && prec != TOK_BF16) || view_mode(view) < 0 || Cin < 1 ||
+      Cout < 1)
+    return fail(TOK_EINVAL, "bad argument");
+  const int mode = view_mode(view);
+  if (!wgrad_op_shape(mode, N, Ti, Hi, Wi, To, Ho, Wo)) return fail(TOK_ESHAPE, "input / output shapes do not match the view");
+  const int P = prec == TOK_BF16 ? P_BF16 : P_F32, CH = P == P_BF16 ? 32 : 16;
+  int sp;
+  const size_t need = wgrad_op_bytes(P, mode, N, To, Ho, Wo, Cin, Cout, &sp);
+  if (need > ws_bytes) return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+  WgradLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x; a.N = N; a.Ti = Ti; a.Hi = Hi; a.Wi = Wi; a.x_chunks = cdiv(Cin, CH);
+  a.dy = dy; a.To = To; a.Ho = Ho; a.Wo = Wo; a.dy_chunks = cdiv(Cout, CH);
+  a.Cout = Cout; a.Cin = Cin; a.view = mode; a.prec = P; a.splits = sp;
+  a.partial = static_cast<float*>(ws);
+  a.bpartial = reinterpret_cast<float*>(static_cast<char*>(ws) + align256((size_t)sp * 27 * Cout * Cin * 4));
+  TOK_HIP(launch_wgrad(a, s));
+  TOK_HIP(launch_wgrad_reduce(a.partial, a.bpartial, sp, Cout, Cin, dw, db, s));
   return TOK_OK;
 }
 

@@ -177,6 +177,28 @@ class TokModel:
         return dict(dweights=dweights, dx=dxt)
 
 
+def conv3d_wgrad(x: torch.Tensor, dy: torch.Tensor, shape_x, shape_y, Cin: int, Cout: int, view: int,
+                 precision: str = "bf16", with_bias: bool = True):
+    """tok_conv3d_wgrad on chunked-layout device tensors x, dy (float32 or
+    bfloat16 storage); shape_x = (N, Ti, Hi, Wi), shape_y = (N, To, Ho, Wo).
+    Returns (dw float32 (Cout, Cin, 3, 3, 3), db float32 (Cout) or None)."""
+    N, Ti, Hi, Wi = shape_x
+    _, To, Ho, Wo = shape_y
+    prec = PRECISIONS[precision]
+    dev = x.device
+    n = C.c_size_t()
+    lb = L.lib()
+    L.check("tok_conv3d_wgrad_workspace_size", lb.tok_conv3d_wgrad_workspace_size(
+        prec, view, N, To, Ho, Wo, Cin, Cout, C.byref(n)))
+    ws = torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+    dw = torch.empty((Cout, Cin, 3, 3, 3), dtype=torch.float32, device=dev)
+    db = torch.empty(Cout, dtype=torch.float32, device=dev) if with_bias else None
+    L.check("tok_conv3d_wgrad", lb.tok_conv3d_wgrad(
+        prec, view, _ptr(x), N, Ti, Hi, Wi, Cin, _ptr(dy), To, Ho, Wo, Cout, _ptr(dw), _ptr(db), _ptr(ws),
+        ws.numel(), _stream(dev)))
+    return dw, db
+
+
 class TokenizerLoss(torch.autograd.Function):
     """L(params) of the training objective with the library's hand-written
     backward: forward runs tok_train_forward (after loading `params` into the
