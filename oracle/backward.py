@@ -202,11 +202,19 @@ def train_forward(u8, p, keep=None, frozen=None):
     return loss, tape
 
 
-def train_backward(tape, p):
-    """Hand-written adjoint of train_forward: returns (grads dict, dx)."""
+def train_backward(tape, p, gx_hat=None):
+    """Hand-written adjoint of train_forward: returns (grads dict, dx).
+
+    gx_hat: optional dL/dx_hat to use instead of the l1 subgradient
+    sign(x_hat - x) / numel.  The l1 term is not differentiable where
+    x_hat = x (its subgradient there is any value in [-1, 1] / numel), so a
+    caller can evaluate the gradient for another valid choice at such pixels;
+    everything after the seed is the same adjoint.
+    """
     grads = {}
     x, xhat = tape["x"], tape["xhat"]
-    gx_hat = np.sign(xhat - x) / xhat.size
+    if gx_hat is None:
+        gx_hat = np.sign(xhat - x) / xhat.size
     gw, gb = conv3d_wgrad(tape["r2"], gx_hat, p["dec.conv_out.w"].shape)
     grads["dec.conv_out.w"], grads["dec.conv_out.b"] = gw, gb
     g = conv3d_dgrad(gx_hat, p["dec.conv_out.w"], tape["r2"].shape)

@@ -148,16 +148,22 @@ __device__ __forceinline__ void mfma_quad(f32x4& acc, const uint4& wq, const uin
   }
 }
 
-// fp8 operand of one lane for the K = 128 MFMA: the 32 bytes (channels
-// 32 hb .. 32 hb + 31 of a 64-channel row) in logical quads 2 hb and 2 hb + 1.
-__device__ __forceinline__ i32x8 ld_fp8_half(const uint4* base, int row, int hb) {
-  const uint4 q0 = base[row * 4 + ((2 * hb) ^ swz(row))];
-  const uint4 q1 = base[row * 4 + ((2 * hb + 1) ^ swz(row))];
+// Operands of the K = 128 fp8 MFMA.  Lane group g (lanes 16 g .. 16 g + 15)
+// holds 32 bytes per row / column; the hardware applies E8M0 scale block s
+// (the byte supplied by lane 16 s + row / column) to bytes 0-15 (s = 0, 1) or
+// 16-31 (s = 2, 3) of lane groups 0 and 1 (even s) or 2 and 3 (odd s).  With
+// two taps x 64 channels per MFMA, lane group g takes tap g >> 1 and, so that
+// every scale block is one tap's 32-channel block, the channel quads h and
+// 2 + h (h = g & 1) of its 64-channel row: block s then covers channels
+// 32 (s >> 1) .. + 31 of tap s & 1.
+__device__ __forceinline__ i32x8 ld_fp8_pair(const uint4* base, int row, int h) {
+  const uint4 q0 = base[row * 4 + (h ^ swz(row))];
+  const uint4 q1 = base[row * 4 + ((2 + h) ^ swz(row))];
   return i32x8{(int)q0.x, (int)q0.y, (int)q0.z, (int)q0.w, (int)q1.x, (int)q1.y, (int)q1.z, (int)q1.w};
 }
 
 // D += A x B on e4m3 operands with K = 128: A (weights) unscaled, B
-// (activations) scaled per lane by the E8M0 byte sb.
+// (activations) scaled by the E8M0 bytes sb (this lane's scale block).
 __device__ __forceinline__ void mfma_fp8(f32x4& acc, const i32x8& w, const i32x8& x, int sb) {
   acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, sb);
 }
@@ -353,23 +359,25 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   // blocks by the NB output-channel blocks.
   auto compute = [&](int buf) {
     if constexpr (F8) {
-      // K = 128 per MFMA = two taps x 64 channels: lane group g4 takes tap
-      // 2 pr + (g4 >> 1), channels 32 (g4 & 1) .. +31, with its scale byte.
-      const int hb = g4 & 1;
+      // K = 128 per MFMA = two taps x 64 channels (see ld_fp8_pair): data of
+      // tap 2 pr + (g4 >> 1), channel quads h, 2 + h; the scale this lane
+      // supplies is that of tap 2 pr + (g4 & 1), 32-channel block g4 >> 1.
+      const int h = g4 & 1, sblk = g4 >> 1;
       if constexpr (MODE == CM_UPF) {
         const int ph = wave >> 1, pw = wave & 1;
 #pragma unroll 1
         for (int pr = 0; pr < 2; ++pr) {
-          const int tap = 2 * pr + (g4 >> 1);
-          const int dh = tap >> 1, dw = tap & 1;
+          const int tap = 2 * pr + (g4 >> 1), stap = 2 * pr + h;
+          const int dh = tap >> 1, dw = tap & 1, sdh = stap >> 1, sdw = stap & 1;
           i32x8 wq[NB];
 #pragma unroll
-          for (int b = 0; b < NB; ++b) wq[b] = ld_fp8_half(lds_w[buf], (wave * 4 + tap) * NT + b * 16 + l16, hb);
+          for (int b = 0; b < NB; ++b) wq[b] = ld_fp8_pair(lds_w[buf], (wave * 4 + tap) * NT + b * 16 + l16, h);
 #pragma unroll
           for (int m = 0; m < MB; ++m) {
             const int row = ((m >> 1) + dh + ph) * G::HW + ((m & 1) * 16 + l16 + dw + pw);
-            const i32x8 aq = ld_fp8_half(lds_a[buf], row, hb);
-            const int sb = (lds_sc[row] >> (8 * hb)) & 255;
+            const int srow = ((m >> 1) + sdh + ph) * G::HW + ((m & 1) * 16 + l16 + sdw + pw);
+            const i32x8 aq = ld_fp8_pair(lds_a[buf], row, h);
+            const int sb = (lds_sc[srow] >> (8 * sblk)) & 255;
 #pragma unroll
             for (int b = 0; b < NB; ++b) mfma_fp8(acc[m][b], wq[b], aq, sb);
           }
@@ -378,22 +386,21 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
 #pragma unroll 1
         for (int pr = 0; pr < 5; ++pr) {
           const int tp = 2 * pr + (g4 >> 1);
-          const bool tv = tp < 9;  // the 10th "tap" has zero weights
-          const int tap = tv ? tp : 8;
-          const int kh = tap / 3, kw = tap % 3;
+          const bool tv = tp < 9;  // the 10th "tap" has zero weights (its data and scale: tap 8's)
+          const int tap = tv ? tp : 8, stap = min(2 * pr + h, 8);
+          const int kh = tap / 3, kw = tap % 3, skh = stap / 3, skw = stap % 3;
           i32x8 wq[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            wq[b] = ld_fp8_half(lds_w[buf], tap * NT + b * 16 + l16, hb);
+            wq[b] = ld_fp8_pair(lds_w[buf], tap * NT + b * 16 + l16, h);
             if (!tv) wq[b] = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
           }
 #pragma unroll
           for (int m = 0; m < MB; ++m) {
             int i, j;
             out_local<MODE>(wave, m, l16, &i, &j);
-            const int row = act_row<MODE>(i, j, kh, kw);
-            const i32x8 aq = ld_fp8_half(lds_a[buf], row, hb);
-            const int sb = (lds_sc[row] >> (8 * hb)) & 255;
+            const i32x8 aq = ld_fp8_pair(lds_a[buf], act_row<MODE>(i, j, kh, kw), h);
+            const int sb = (lds_sc[act_row<MODE>(i, j, skh, skw)] >> (8 * sblk)) & 255;
 #pragma unroll
             for (int b = 0; b < NB; ++b) mfma_fp8(acc[m][b], wq[b], aq, sb);
           }
@@ -878,7 +885,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradLaunch a) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient on bf16 MFMA (bf16 operands, Cin and Cout multiples of 64).
+// Weight gradient on bf16 MFMA (bf16 operands; channel counts are padded to
+// 64-channel tiles, empty 16-channel blocks are skipped).
 // D[o][i] += dy[p][o] x~[p + tap][i] with K = output positions: 16x16x32 bf16
 // MFMAs, A = dy (rows o), B = x (columns i).  Block = (temporal tap, 64
 // output channels, 64 input channels, split); wave w owns input channels
@@ -942,13 +950,16 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g4 = lane >> 4;
-  const int ic_tiles = a.Cin / 64, oc_tiles = a.Cout / 64;
+  const int ic_tiles = (a.Cin + 63) / 64, oc_tiles = (a.Cout + 63) / 64;
   int v = blockIdx.x;
   const int sp = v % a.splits; v /= a.splits;
   const int ot = v % oc_tiles; v /= oc_tiles;
   const int it = v % ic_tiles; v /= ic_tiles;
   const int kt = v;
   const int tiles_h = (a.Ho + G::TH - 1) / G::TH, tiles_w = (a.Wo + 63) / 64;
+  const int nob = min(4, (a.Cout - ot * 64 + 15) / 16);      // output-channel blocks holding channels
+  const bool wave_cols = it * 64 + wave * 16 < a.Cin;          // this wave's input channels exist
+  const int dy_ch = a.dy_chunks * 32, x_ch = a.x_chunks * 32;  // channels stored (zeros past Cout / Cin)
   const long long items = (long long)a.N * a.To * tiles_h * tiles_w;
   const long long i0 = items * sp / a.splits, i1 = items * (sp + 1) / a.splits;
   const bool bias_sum = a.bpartial && kt == 0 && it == 0;
@@ -985,7 +996,7 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
         const int oh = h0 + p / 64, ow = w0 + p % 64;
         const int oc = ot * 64 + cb * 8;  // 8 channels inside one 32-channel chunk
         vv[k] = make_uint4(0, 0, 0, 0);
-        if (oh < a.Ho && ow < a.Wo)
+        if (oh < a.Ho && ow < a.Wo && oc < dy_ch)
           vv[k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + oc / 32) * plane_y + (size_t)oh * a.Wo + ow) * 4 +
                       (oc % 32) / 8];
       }
@@ -1015,7 +1026,7 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
         }
         const int ic = it * 64 + cb * 8;
         vv[k] = make_uint4(0, 0, 0, 0);
-        if (q < 66 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi)
+        if (q < 66 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ic < x_ch)
           vv[k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ic / 32) * plane_x + (size_t)hs * a.Wi + ws) * 4 +
                      (ic % 32) / 8];
       }
@@ -1031,7 +1042,7 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
     // ---- K loop over the item's positions, 32 per step ----
     const uint16_t* xrow = s_x + (wave * 16 + l16) * Lp::XS;
 #pragma unroll 1
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int ks = 0; ks < (wave_cols ? KS : 0); ++ks) {
       const int pr = (ks * 32) / 64, pc = (ks * 32) % 64 + 8 * g4;  // this lane's 8 positions: row pr, cols pc..pc+7
       bf16x8 av[4];
 #pragma unroll
@@ -1046,7 +1057,8 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
         const uint4 xv = ld8_bf16(xrow, (row * G::PLANES + pl) * kWmCols + col, mis);
         const bf16x8 bv = __builtin_bit_cast(bf16x8, xv);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b], bv, acc[b][t], 0, 0, 0);
+        for (int b = 0; b < 4; ++b)
+          if (b < nob) acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b], bv, acc[b][t], 0, 0, 0);
       }
     }
   }
@@ -1058,9 +1070,10 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int oc = ot * 64 + b * 16 + 4 * g4 + r, icn = it * 64 + wave * 16 + l16;
-        a.partial[((((size_t)sp * 3 + kt) * 9 + t) * a.Cout + oc) * a.Cin + icn] = acc[b][t][r];
+        if (oc < a.Cout && icn < a.Cin)
+          a.partial[((((size_t)sp * 3 + kt) * 9 + t) * a.Cout + oc) * a.Cin + icn] = acc[b][t][r];
       }
-  if (bias_sum && tid < 64) a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = bsum;
+  if (bias_sum && tid < 64 && ot * 64 + tid < a.Cout) a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = bsum;
 }
 
 // Sums the per-split partials in split order: weights into the canonical
@@ -1131,12 +1144,12 @@ hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
 }
 
 namespace {
-bool wgrad_uses_mfma_bf16(int prec, int Cout, int Cin) { return prec == P_BF16 && Cin % 64 == 0 && Cout % 64 == 0; }
+bool wgrad_uses_mfma_bf16(int prec, int Cout, int Cin) { (void)Cout; (void)Cin; return prec == P_BF16; }
 }  // namespace
 
 int wgrad_blocks_per_split(int prec, int view, int Cout, int Cin) {
   (void)view;
-  if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) return 3 * (Cin / 64) * (Cout / 64);
+  if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) return 3 * ((Cin + 63) / 64) * ((Cout + 63) / 64);
   return 3 * ((Cin + 31) / 32) * ((Cout + 63) / 64);
 }
 

@@ -3,8 +3,9 @@ the FP64 oracle's hand-written adjoint (oracle/backward.py, itself pinned by
 dot-product tests, torch autograd and central finite differences).
 
 Bars: FP32 loss within rel 1e-5 and every parameter tensor's gradient within
-relative L2 error 1e-4 of the oracle's; BF16 within the bounds stated in its
-test.  The loss is a mean, so at any size the gradient of a batch is the mean
+relative L2 error 1e-4 of the oracle's, for the oracle's choice of the l1
+subgradient's sign at pixels where x_hat is within the reconstruction
+tolerance of x (see L1_BAND); BF16 within the bounds stated in its test.  The loss is a mean, so at any size the gradient of a batch is the mean
 of its clips' gradients; that property is checked at the training benchmark
 size, where the oracle is too slow."""
 import functools
@@ -23,6 +24,12 @@ pytestmark = pytest.mark.gpu
 
 F32_LOSS_RTOL = 1e-5
 F32_GRAD_REL_L2 = 1e-4
+# The l1 subgradient sign(x_hat - x) is set-valued where x_hat = x: at pixels
+# whose oracle residual is within the FP32 reconstruction tolerance, the GPU's
+# x_hat may fall on the other side of x, and either sign is a correct
+# subgradient.  The adjoint is affine in the seed, so every such choice is the
+# oracle gradient plus a sum of per-pixel flip corrections.
+L1_BAND = G.F32_RECON_TOL
 
 
 @pytest.fixture(scope="module")
@@ -48,6 +55,38 @@ def oracle_step(seeds, T, H, W, rate):
     loss, tape = B.train_forward(u8, p, keep)
     grads, dx = B.train_backward(tape, p)
     return loss, tape, grads, dx, keep
+
+
+def flat_grads(grads, dx):
+    return np.concatenate([synth.flatten_weights(grads).astype(np.float64), dx.ravel()])
+
+
+@functools.lru_cache(maxsize=None)
+def l1_band_flips(seeds, T, H, W, rate):
+    """Oracle gradient changes (weights and dx, flattened) from flipping the
+    l1 sign at each in-band pixel alone."""
+    loss, tape, grads, dx, keep = oracle_step(seeds, T, H, W, rate)
+    p = G.weights64(True)
+    d = tape["xhat"] - tape["x"]
+    zero = np.zeros_like(d)
+    g0 = flat_grads(*B.train_backward(tape, p, gx_hat=zero))
+    flips = []
+    for ix in np.argwhere(np.abs(d) < L1_BAND):
+        seed = zero.copy()
+        seed[tuple(ix)] = -2.0 * np.sign(d[tuple(ix)]) / d.size
+        flips.append(flat_grads(*B.train_backward(tape, p, gx_hat=seed)) - g0)
+    return flips
+
+
+def best_valid_gradient(gpu_flat, ref_flat, flips):
+    """The oracle gradient for the choice of in-band signs closest to the GPU's."""
+    best, best_e = ref_flat, np.inf
+    for mask in range(1 << len(flips)):
+        cand = ref_flat + sum((f for k, f in enumerate(flips) if mask >> k & 1), np.zeros_like(ref_flat))
+        e = np.linalg.norm(gpu_flat - cand)
+        if e < best_e:
+            best, best_e = cand, e
+    return best
 
 
 def rel_l2(a, b):
@@ -87,13 +126,20 @@ def test_train_step_f32_matches_oracle(tk, seeds, T, H, W, rate):
     np.testing.assert_allclose(g["loss"][0], loss, rtol=F32_LOSS_RTOL)
     np.testing.assert_allclose(g["loss"][1], tape["l1"], rtol=F32_LOSS_RTOL)
     np.testing.assert_allclose(g["loss"][2], tape["commit"], rtol=F32_LOSS_RTOL)
-    gg = grads_by_name(g["dw"])
+    flips = l1_band_flips(seeds, T, H, W, rate)
+    nw = g["dw"].size
+    ref = best_valid_gradient(np.concatenate([g["dw"], g["dx"].ravel()]).astype(np.float64), flat_grads(grads, dx),
+                              flips)
+    print("in-band l1 pixels: %d" % len(flips), flush=True)
+    gg, rg = grads_by_name(g["dw"]), synth.unflatten_weights(ref[:nw])
+    dx = ref[nw:].reshape(dx.shape)
     worst = []
     for name, _, _ in synth.param_spec():
-        e = rel_l2(gg[name], grads[name])
+        e = rel_l2(gg[name], rg[name])
         worst.append((e, name))
+    for e, name in worst:
+        print("  grad rel-L2 %-22s %.3e" % (name, e), flush=True)
     worst.sort(reverse=True)
-    print("worst gradient rel-L2:", worst[:4], flush=True)
     assert worst[0][0] <= F32_GRAD_REL_L2, worst[:4]
     assert rel_l2(g["dx"], dx) <= F32_GRAD_REL_L2
 
