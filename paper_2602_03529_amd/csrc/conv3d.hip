@@ -905,7 +905,7 @@ template <int VIEW> struct WMGeo;
 template <> struct WMGeo<CM_S1> { static constexpr int TH = 2, ROWS = 4, PLANES = 1; };
 template <> struct WMGeo<CM_UP> { static constexpr int TH = 2, ROWS = 4, PLANES = 1; };
 template <> struct WMGeo<CM_S2> { static constexpr int TH = 1, ROWS = 3, PLANES = 2; };
-constexpr int kWmCols = 72;   // halo columns per plane row (>= 66, multiple of 8)
+constexpr int kWmCols = 80;   // halo columns per plane row: >= 66, multiple of 8, + 8 for the read window
 
 template <int VIEW> struct WMLds {
   using G = WMGeo<VIEW>;
@@ -930,18 +930,25 @@ __device__ __forceinline__ void transpose8x8_bf16(const uint4* v, uint4* w) {
   }
 }
 
-// 8 bf16 at element offset e0 + mis (e0 a multiple of 8) of an LDS array.
-__device__ __forceinline__ uint4 ld8_bf16(const uint16_t* base, int e0, int mis) {
-  const uint32_t* d = reinterpret_cast<const uint32_t*>(base + e0);
-  if (mis == 0) return *reinterpret_cast<const uint4*>(d);
-  if (mis == 2) return make_uint4(d[1], d[2], d[3], d[4]);
-  const uint32_t w0 = d[0], w1 = d[1], w2 = d[2], w3 = d[3], w4 = d[4];
-  return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2), __builtin_amdgcn_alignbyte(w2, w1, 2),
-                    __builtin_amdgcn_alignbyte(w3, w2, 2), __builtin_amdgcn_alignbyte(w4, w3, 2));
+// 16 bf16 from element offset e0 (a multiple of 8) of an LDS array: two
+// aligned 16-byte reads, from which the 8 elements at offset 0, 1 or 2 are
+// taken in registers (no unaligned LDS access).
+struct Win16 { uint4 lo, hi; };
+__device__ __forceinline__ Win16 ld16_bf16(const uint16_t* base, int e0) {
+  const uint4* q = reinterpret_cast<const uint4*>(base + e0);
+  return Win16{q[0], q[1]};
+}
+template <int MIS>
+__device__ __forceinline__ uint4 win_at(const Win16& w) {
+  if constexpr (MIS == 0) return w.lo;
+  else if constexpr (MIS == 2) return make_uint4(w.lo.y, w.lo.z, w.lo.w, w.hi.x);
+  else
+    return make_uint4(__builtin_amdgcn_alignbyte(w.lo.y, w.lo.x, 2), __builtin_amdgcn_alignbyte(w.lo.z, w.lo.y, 2),
+                      __builtin_amdgcn_alignbyte(w.lo.w, w.lo.z, 2), __builtin_amdgcn_alignbyte(w.hi.x, w.lo.w, 2));
 }
 
 template <int VIEW>
-__global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
+__global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
   using G = WMGeo<VIEW>;
   using Lp = WMLds<VIEW>;
   constexpr int NPOS = Lp::NPOS, KS = NPOS / 32;
@@ -963,7 +970,8 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
   const long long items = (long long)a.N * a.To * tiles_h * tiles_w;
   const long long i0 = items * sp / a.splits, i1 = items * (sp + 1) / a.splits;
   const bool bias_sum = a.bpartial && kt == 0 && it == 0;
-  float bsum = 0.f;
+  float bsum = 0.f;  // thread t: channel t >> 2, positions (t & 3) + 4 k of each item
+  __shared__ float s_bias[4][64];
 
   f32x4 acc[4][9];
 #pragma unroll
@@ -986,9 +994,10 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
     else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
     else ts = (max(to + kt - 2, 0) + 1) >> 1;
     __syncthreads();
-    // ---- stage dy: blocks of 8 positions x 8 output channels ----
+    // ---- stage dy: blocks of 8 positions x 8 output channels (position block
+    // fastest across lanes: their transposed 16-byte stores hit distinct banks) ----
     for (int blk = tid; blk < (NPOS / 8) * 8; blk += 256) {
-      const int pb = blk >> 3, cb = blk & 7;
+      const int pb = blk % (NPOS / 8), cb = blk / (NPOS / 8);
       uint4 vv[8], ww[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -1005,11 +1014,11 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
       for (int k = 0; k < 8; ++k) *reinterpret_cast<uint4*>(&s_dy[(cb * 8 + k) * Lp::DYS + pb * 8]) = ww[k];
     }
     // ---- stage the input halo: blocks of 8 columns (of one plane row) x 8 input channels ----
-    constexpr int QB = kWmCols / 8;
+    constexpr int QB = 9;  // column blocks holding the 66 halo columns
     for (int blk = tid; blk < G::ROWS * G::PLANES * QB * 8; blk += 256) {
       int r = blk;
-      const int cb = r % 8; r /= 8;
       const int qb = r % QB; r /= QB;
+      const int cb = r % 8; r /= 8;
       const int pl = r % G::PLANES; r /= G::PLANES;
       const int hr = r;
       uint4 vv[8], ww[8];
@@ -1036,8 +1045,8 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
         *reinterpret_cast<uint4*>(&s_x[(cb * 8 + k) * Lp::XS + (hr * G::PLANES + pl) * kWmCols + qb * 8]) = ww[k];
     }
     __syncthreads();
-    if (bias_sum && tid < 64) {
-      for (int p = 0; p < NPOS; ++p) bsum += __uint_as_float((uint32_t)s_dy[tid * Lp::DYS + p] << 16);
+    if (bias_sum) {
+      for (int p = tid & 3; p < NPOS; p += 4) bsum += __uint_as_float((uint32_t)s_dy[(tid >> 2) * Lp::DYS + p] << 16);
     }
     // ---- K loop over the item's positions, 32 per step ----
     const uint16_t* xrow = s_x + (wave * 16 + l16) * Lp::XS;
@@ -1048,17 +1057,28 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
 #pragma unroll
       for (int b = 0; b < 4; ++b)
         av[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_dy[(b * 16 + l16) * Lp::DYS + ks * 32 + 8 * g4]));
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int kh = t / 3, kw = t % 3;
-        int row, pl, col, mis;
-        if constexpr (VIEW == CM_S2) { row = 2 * pr + kh; pl = kw & 1; col = pc; mis = kw >> 1; }
-        else { row = pr + kh; pl = 0; col = pc; mis = kw; }
-        const uint4 xv = ld8_bf16(xrow, (row * G::PLANES + pl) * kWmCols + col, mis);
+      auto mma = [&](int t, const uint4& xv) {
         const bf16x8 bv = __builtin_bit_cast(bf16x8, xv);
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           if (b < nob) acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b], bv, acc[b][t], 0, 0, 0);
+      };
+#pragma unroll
+      for (int kh = 0; kh < 3; ++kh) {
+        if constexpr (VIEW == CM_S2) {
+          // columns 2c + kw: kw = 0, 2 from the even plane (offset 0, 1), kw = 1 from the odd plane
+          const int row = 2 * pr + kh;
+          const Win16 ev = ld16_bf16(xrow, (row * 2 + 0) * kWmCols + pc);
+          const Win16 od = ld16_bf16(xrow, (row * 2 + 1) * kWmCols + pc);
+          mma(kh * 3 + 0, win_at<0>(ev));
+          mma(kh * 3 + 1, win_at<0>(od));
+          mma(kh * 3 + 2, win_at<1>(ev));
+        } else {
+          const Win16 w = ld16_bf16(xrow, (pr + kh) * kWmCols + pc);
+          mma(kh * 3 + 0, win_at<0>(w));
+          mma(kh * 3 + 1, win_at<1>(w));
+          mma(kh * 3 + 2, win_at<2>(w));
+        }
       }
     }
   }
@@ -1073,7 +1093,12 @@ __global__ void __launch_bounds__(256) wgrad_mfma_kernel(WgradLaunch a) {
         if (oc < a.Cout && icn < a.Cin)
           a.partial[((((size_t)sp * 3 + kt) * 9 + t) * a.Cout + oc) * a.Cin + icn] = acc[b][t][r];
       }
-  if (bias_sum && tid < 64 && ot * 64 + tid < a.Cout) a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = bsum;
+  if (bias_sum) {
+    s_bias[tid & 3][tid >> 2] = bsum;
+    __syncthreads();
+    if (tid < 64 && ot * 64 + tid < a.Cout)
+      a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = ((s_bias[0][tid] + s_bias[1][tid]) + s_bias[2][tid]) + s_bias[3][tid];
+  }
 }
 
 // Sums the per-split partials in split order: weights into the canonical
