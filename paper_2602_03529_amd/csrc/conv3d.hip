@@ -62,6 +62,12 @@ template <> struct Geo<CM_UP> {
   static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
 template <> struct Geo<CM_S1T> : Geo<CM_S1> {};
+// im2col first layer: the "halo" is the tile itself (one row per output
+// position), one tap, one stage per 96-wide K chunk.
+template <> struct Geo<CM_I2C> {
+  static constexpr int WR = 2, TW = 64, TH = 8, HH = TH, HW = TW;
+  static constexpr int MB = 8, WT = 1, KTS = 1;
+};
 
 // Polyphase upsample conv: wave w owns output phase (h & 1, w & 1) = (w >> 1, w & 1)
 // of the tile, i.e. 4 source rows x 32 source columns = 8 blocks; a stage holds
@@ -83,7 +89,7 @@ constexpr bool kS1Tall = TOK_S1_TALL != 0;
 template <int MODE>
 __device__ __forceinline__ void out_local(int wave, int m, int l16, int* i, int* j) {
   using G = Geo<MODE>;
-  if constexpr ((MODE == CM_S1 || MODE == CM_S1T) && kS1Tall) {
+  if constexpr ((MODE == CM_S1 || MODE == CM_S1T || MODE == CM_I2C) && kS1Tall) {
     *i = 4 * (wave >> 1) + (m >> 1);
     *j = 32 * (wave & 1) + 16 * (m & 1) + l16;
   } else if constexpr (MODE == CM_UPF) {
@@ -195,9 +201,13 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   static_assert(OUT_KIND != OUT_FP8 || (F8 && !STATS && NB == 4), "fp8 output: fp8 kernels, no statistics");
   constexpr int SCN = F8 ? HALO : 1;      // fp8: two E8M0 bytes per halo row
 
+  constexpr int PXN = MODE == CM_I2C ? 3 * (G::TH + 2) * (G::TW + 2) * 4 : 1;  // normalised pixel halo
+  static_assert(MODE != CM_I2C || (IN_KIND == IN_U8 && !DB && !F8), "im2col: uint8 input");
+
   __shared__ uint4 lds_a[NBUF][HQ];
   __shared__ uint4 lds_w[NBUF][WQ];
   __shared__ uint16_t lds_sc[SCN];
+  __shared__ float lds_px[PXN];
   __shared__ float red[kWaves][32];
   __shared__ float gmean[32];
 
@@ -312,46 +322,56 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
     }
   };
 
-  // uint8 RGB input (first layer): x / 127.5 - 1 in channels 0..2 of quad 0,
-  // zeros elsewhere; converted in registers, so staged synchronously.
-  auto stage_u8 = [&](int st) {
-    constexpr int NHQ = (HQ + kThreads - 1) / kThreads;
-    const int kt = st / a.in_chunks;
+  // im2col first layer.  Once per tile: the 3 causal input frames' pixel
+  // halos (TH+2 x TW+2), normalised to x/127.5 - 1 (0 outside the frame), as
+  // floats [frame][row][col][4].  Per stage (K chunk): weights by direct
+  // load; each thread writes quad (tid & 3) of rows (tid >> 2) + 64 u, i.e.
+  // QE consecutive K entries k = (kt*9 + kh*3 + kw)*3 + c of one position.
+  constexpr int PXW = G::TW + 2, PXH = G::TH + 2;
+  auto stage_px = [&]() {
+    for (int e = tid; e < 3 * PXH * PXW; e += kThreads) {
+      const int f = e / (PXH * PXW), r = (e / PXW) % PXH, c = e % PXW;
+      const int hs = h0 - 1 + r, ws = w0 - 1 + c;
+      const int g = max(a.go0 + to + f - 2, 0) - a.gi0;  // causal clamp of the input frame
+      float px[3] = {0.f, 0.f, 0.f};
+      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
+        const uint8_t* pp = reinterpret_cast<const uint8_t*>(a.in) + (((size_t)n * a.Ti + g) * a.Hi * a.Wi +
+                                                                          (size_t)hs * a.Wi + ws) * 3;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) px[ch] = (float)pp[ch] / 127.5f - 1.0f;
+      }
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) lds_px[e * 4 + ch] = px[ch];
+      lds_px[e * 4 + 3] = 0.f;
+    }
+  };
+  auto stage_i2c = [&](int st) {
     const uint4* wsrc = wbase + (size_t)st * WQ;
 #pragma unroll
     for (int base = wave * 64; base < WQ; base += kThreads) lds_dma16(wsrc + base + lane, &lds_w[0][base]);
-    const uint8_t* src = reinterpret_cast<const uint8_t*>(a.in) + ((size_t)n * a.Ti + src_frame(kt)) * plane_in * 3;
-    uint32_t px[NHQ];
-    uint32_t inb = 0;
+    constexpr int QE = O::QE;
+    const int q = tid & 3;
+    int off[QE];
 #pragma unroll
-    for (int k = 0; k < NHQ; ++k) {
-      const int e = tid + k * kThreads;
-      px[k] = 0;
-      if (e < HQ && (e & 3) == 0) {
-        int hs, ws;
-        halo_src<MODE>(e >> 2, h0, w0, &hs, &ws);
-        if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
-          const uint8_t* pp = src + ((size_t)hs * a.Wi + ws) * 3;
-          px[k] = (uint32_t)pp[0] | ((uint32_t)pp[1] << 8) | ((uint32_t)pp[2] << 16);
-          inb |= 1u << k;
-        }
-      }
+    for (int x = 0; x < QE; ++x) {
+      const int k = st * O::CH + q * QE + x;
+      const int tap = k / 3, ch = k % 3;
+      const int kt = tap / 9, kh = (tap / 3) % 3, kw = tap % 3;
+      off[x] = k < 81 ? ((kt * PXH + kh) * PXW + kw) * 4 + ch : -1;
     }
 #pragma unroll
-    for (int k = 0; k < NHQ; ++k) {
-      const int e = tid + k * kThreads;
-      if (e < HQ) {
-        const int p = e >> 2, q = e & 3;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (inb & (1u << k)) {
-          const float r = (float)(px[k] & 0xff) / 127.5f - 1.0f;
-          const float g = (float)((px[k] >> 8) & 0xff) / 127.5f - 1.0f;
-          const float bch = (float)((px[k] >> 16) & 0xff) / 127.5f - 1.0f;
-          if constexpr (PREC == P_BF16) val = make_uint4(pack_bf16(r, g), pack_bf16(bch, 0.f), 0, 0);
-          else val = make_uint4(__float_as_uint(r), __float_as_uint(g), __float_as_uint(bch), 0);
-        }
-        lds_a[0][p * 4 + (q ^ swz(p))] = val;
-      }
+    for (int u = 0; u < (G::TH * G::TW) / 64; ++u) {
+      const int row = (tid >> 2) + 64 * u;
+      const int base = ((row / G::TW) * PXW + (row % G::TW)) * 4;
+      float v[QE];
+#pragma unroll
+      for (int x = 0; x < QE; ++x) v[x] = off[x] >= 0 ? lds_px[base + off[x]] : 0.f;
+      uint4 val;
+      if constexpr (PREC == P_BF16)
+        val = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+      else
+        val = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3]));
+      lds_a[0][row * 4 + (q ^ swz(row))] = val;
     }
   };
 
@@ -405,6 +425,24 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
             for (int b = 0; b < NB; ++b) mfma_fp8(acc[m][b], wq[b], aq, sb);
           }
         }
+      }
+      return;
+    }
+    if constexpr (MODE == CM_I2C) {
+      uint4 wq[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int row = b * 16 + l16;
+        wq[b] = lds_w[buf][row * 4 + (g4 ^ swz(row))];
+      }
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        int i, j;
+        out_local<MODE>(wave, m, l16, &i, &j);
+        const int row = i * G::TW + j;
+        const uint4 aq = lds_a[buf][row * 4 + (g4 ^ swz(row))];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
       }
       return;
     }
@@ -496,13 +534,16 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
       compute(st & 1);
     }
   } else {
+    if constexpr (MODE == CM_I2C) {
+      stage_px();
+    }
     for (int st = 0; st < nstages; ++st) {
       if constexpr (MODE == CM_S1T) {
         if (src_frame(st / a.in_chunks) >= a.Ti) continue;  // beyond the last gradient frame (uniform per block)
       }
       __syncthreads();
-      if constexpr (IN_KIND == IN_ACT) issue_async(st, 0);
-      else stage_u8(st);
+      if constexpr (MODE == CM_I2C) stage_i2c(st);
+      else issue_async(st, 0);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // direct-to-LDS loads have landed
       __syncthreads();
       compute(0);
@@ -711,8 +752,8 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   // The configurations the tokenizer uses.
   const bool res = a.resid != nullptr, st = a.stats != nullptr;
   if (a.in_kind == IN_U8) {
-    if (a.mode == CM_S1 && a.nt == 64 && a.out_kind == OUT_ACT && !res && st)
-      return launch_one<PREC, CM_S1, 4, IN_U8, OUT_ACT, false, true>(a, s);
+    if (a.mode == CM_I2C && a.nt == 64 && a.out_kind == OUT_ACT && !res && st)
+      return launch_one<PREC, CM_I2C, 4, IN_U8, OUT_ACT, false, true>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.out_kind == OUT_RGB32) {
@@ -1283,6 +1324,16 @@ __device__ float pack_value(const float* __restrict__ w, const PackGeom& g, size
         for (int kw = fold_lo(pw, dw); kw <= fold_hi(pw, dw); ++kw) v += W(co, ci, kt, kh, kw);
     return v;
   }
+  if (g.mode == CM_I2C) {
+    // [ct][chunk][o][quad][QE]: K index k = (kt*9 + kh*3 + kw)*3 + c, zero past 81
+    const int ck = (int)(e % g.chunks); e /= g.chunks;
+    const int ct = (int)e;
+    const int q = pq ^ swz(o);
+    const int co = ct * g.nt + o, k = ck * g.CH + q * g.QE + x;
+    if (co >= g.Cout || k >= 81) return 0.f;
+    const int tp = k / 3;
+    return W(co, k % 3, tp / 9, (tp / 3) % 3, tp % 3);
+  }
   const int tap = (int)(e % 9); e /= 9;
   const int ck = (int)(e % g.chunks); e /= g.chunks;
   const int kt = (int)(e % 3); e /= 3;  // CM_S1T: gradient frame offset dt
@@ -1369,8 +1420,10 @@ PackGeom pack_geom(int Cout, int Cin, int prec, int mode, size_t* elems) {
   g.co = co;
   g.nt = co >= 64 ? 64 : 16;
   g.chunks = (ci + g.CH - 1) / g.CH;
+  if (mode == CM_I2C) g.chunks = kI2cK / g.CH;  // K = 27 taps x 3 channels, padded
   if (mode == CM_UPF) g.R = 2 * 2 * g.chunks * 16;
   else if (mode == CM_S1T) g.R = 2 * 3 * g.chunks * 9;
+  else if (mode == CM_I2C) g.R = g.chunks;
   else g.R = 3 * g.chunks * 9;
   const size_t tiles = (size_t)((co + g.nt - 1) / g.nt);
   *elems = tiles * g.R * g.nt * g.CH;

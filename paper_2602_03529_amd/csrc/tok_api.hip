@@ -174,7 +174,7 @@ tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_
   a.in = in;
   a.N = N; a.Ti = iw.Tb; a.Hi = Hi; a.Wi = Wi;
   a.gi0 = iw.g0;
-  a.in_chunks = cdiv(Cin, CH);
+  a.in_chunks = mode == CM_I2C ? kI2cK / CH : cdiv(Cin, CH);
   a.Cin = Cin;
   a.wpk = m->wpk[layer];
   a.bias = m->bias[layer];
@@ -656,7 +656,7 @@ tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W
   for (int L0 = 0; L0 < d.T2; L0 += p.CL) {
     const int L1 = std::min(L0 + p.CL, d.T2);
     const ChunkWins c = chunk_windows(p, L0, L1);
-    TOK_TRY(conv(m, L_CONV_IN, CM_S1, x, IN_U8, N, pix, H, W, 3, w.l0a(), OUT_ACT, c.l0, H, W, nullptr, w.stats(), s));
+    TOK_TRY(conv(m, L_CONV_IN, conv_mode(L_CONV_IN), x, IN_U8, N, pix, H, W, 3, w.l0a(), OUT_ACT, c.l0, H, W, nullptr, w.stats(), s));
     TOK_TRY(resblocks(m, L_E_RB1_A, N_E_RB1_A, w, d, c.l0, false, chunked, L0, s));
     TOK_TRY(conv(m, L_DOWN1, CM_S2, w.l0a(), IN_ACT, N, c.l0, H, W, 64, w.l1(), OUT_ACT, c.l1, d.H1, d.W1, nullptr,
                  nullptr, s));

@@ -48,6 +48,7 @@ inline bool is_decoder_layer(int l) { return l >= L_PROJ_IN; }
 
 // Addressing mode of each 3x3x3 layer's forward conv.
 inline int conv_mode(int l) {
+  if (l == L_CONV_IN) return CM_I2C;
   if (l == L_DOWN1 || l == L_DOWN2) return CM_S2;
   if (l == L_UP2 || l == L_UP1) return CM_UPF;
   return CM_S1;

@@ -127,7 +127,7 @@ tok_status tconv(const TrainCtx& c, int kid, int mode, const void* wpk, const fl
   a.in = in;
   a.N = c.p.d.N; a.Ti = Ti; a.Hi = Hi; a.Wi = Wi;
   a.gi0 = 0;
-  a.in_chunks = cdiv(Cin, c.CH);
+  a.in_chunks = mode == CM_I2C ? kI2cK / c.CH : cdiv(Cin, c.CH);
   a.Cin = Cin;
   a.wpk = wpk;
   a.bias = bias;
