@@ -26,6 +26,9 @@ Layout: every activation is (N, T, H, W, C) float64 ("NDHWC").
 """
 from __future__ import annotations
 
+import math
+from fractions import Fraction
+
 import numpy as np
 
 GN_GROUPS = 32
@@ -267,7 +270,7 @@ def fsq_boundary_distance(b):
 
 U64 = np.uint64
 GOLDEN = 0x9E3779B97F4A7C15
-DROP_NONE, DROP_BERNOULLI, DROP_ROWS, DROP_EXTERNAL = 0, 1, 2, 3
+DROP_NONE, DROP_BERNOULLI, DROP_ROWS, DROP_EXTERNAL, DROP_SIMILARITY = 0, 1, 2, 3, 4
 ROW_SALT = 0x5A5A5A5A00000000
 
 
@@ -322,6 +325,52 @@ def keep_mask(mode, rate, seed, clip_ids, T2, H2, W2, protect_iframe=False, exte
             keep[n] = (u >= U64(thr)).astype(np.uint8)
     if protect_iframe:
         keep[:, 0] = 1
+    return keep
+
+
+def similarity_order_key(vp, vi):
+    """A key that orders tokens exactly as the cosine similarity of Eq. 3,
+    S = vp . vi / (|vp| |vi|) (S = 0 when either norm is 0): sign(dot) *
+    dot^2 / (|vp|^2 |vi|^2), an exact rational for the integer vectors
+    vp = 4 c_P, vi = 4 c_I (FSQ codes times 4 are integers in [-4, 4])."""
+    dot = int(np.dot(vp, vi))
+    nn = int(np.dot(vp, vp)) * int(np.dot(vi, vi))
+    if nn == 0 or dot == 0:
+        return Fraction(0)
+    return Fraction(dot * dot, nn) * (1 if dot > 0 else -1)
+
+
+def similarity_drop_count(rate, n_p):
+    """Tokens to drop among n_p P tokens: ceil(rate * n_p), rate clamped to [0, 1]."""
+    r = min(max(float(np.float32(rate)), 0.0), 1.0)
+    return min(int(math.ceil(r * n_p)), n_p)
+
+
+def similarity_keep(codes, rate):
+    """keep (N, T2, H2, W2) of similarity-based token selection (Sec. 5,
+    Eq. 3).  Latent frame 0 of a clip is the I-frame token matrix and is
+    never dropped; every later latent frame is a P-frame matrix whose token
+    at (h', w') is scored by its cosine similarity to the I token at the
+    same location.  Per clip, the ceil(rate * N_P) P tokens with the highest
+    similarity are dropped (the paper's threshold tau set by the bandwidth
+    budget, expressed as a drop count), ties going to the lower token index
+    i = (t' H2 + h') W2 + w' first."""
+    c = np.asarray(codes, np.float64)
+    N, T2, H2, W2, _ = c.shape
+    v = np.rint(4.0 * c).astype(np.int64)
+    keep = np.ones((N, T2, H2, W2), np.uint8)
+    n_p = (T2 - 1) * H2 * W2
+    d = similarity_drop_count(rate, n_p)
+    for n in range(N):
+        scored = []
+        for t in range(1, T2):
+            for h in range(H2):
+                for w in range(W2):
+                    scored.append((-similarity_order_key(v[n, t, h, w], v[n, 0, h, w]), (t * H2 + h) * W2 + w))
+        scored.sort()
+        for _, i in scored[:d]:
+            t, rem = divmod(i, H2 * W2)
+            keep[n, t, rem // W2, rem % W2] = 0
     return keep
 
 
