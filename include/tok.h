@@ -78,7 +78,10 @@ typedef enum {
   TOK_DROP_ROWS = 2,       /* one draw per token-matrix row r = t*H2 + h with key
                               0x5A5A5A5A00000000 | r; a dropped row is a lost
                               packet of Sec. 6.2 and zeroes all W2 tokens */
-  TOK_DROP_EXTERNAL = 3    /* keep mask supplied by the caller (device, uint8) */
+  TOK_DROP_EXTERNAL = 3,   /* keep mask supplied by the caller (device, uint8) */
+  TOK_DROP_SIMILARITY = 4  /* similarity-based token selection (Sec. 4.3, Eq. 3):
+                              see tok_select_similar; only tok_encode and the
+                              server take it (it needs the codes and scratch) */
 } tok_drop_mode;
 
 /* Token-drop request.  clip_id0: the hash id of clip 0 of the batch; clip n
@@ -125,8 +128,10 @@ tok_status tok_workspace_size(const tok_model* model, int N, int T, int H, int W
 /* Encoder f_phi followed by FSQ and the token mask, fused.
  * x: uint8 (N,T,H,W,3).  z: float32 pre-quantisation latent or NULL.
  * codes: float32 normalised codes, already multiplied by keep.  idx: int32
- * code indices (a dropped token keeps its true index).  drop: NULL = keep all.
- * keep: uint8 mask output or NULL.  ws: workspace of ws_bytes. */
+ * code indices (a dropped token keeps its true index).  drop: NULL = keep all;
+ * TOK_DROP_SIMILARITY needs codes and runs tok_select_similar on them once
+ * the whole batch is encoded, in the same workspace (tok_workspace_size
+ * covers it).  keep: uint8 mask output or NULL.  ws: workspace of ws_bytes. */
 tok_status tok_encode(tok_model* model, const uint8_t* x, int N, int T, int H, int W, float* z,
                       float* codes, int32_t* idx, const tok_drop_desc* drop, uint8_t* keep,
                       void* ws, size_t ws_bytes, hipStream_t stream);
@@ -139,9 +144,29 @@ tok_status tok_quantize(const float* z, size_t n_tokens, float* codes, int32_t* 
 /* Token dropping alone (Sec. 6.2 zero fill): builds keep (N,T2,H2,W2) from
  * `drop` and multiplies codes (N,T2,H2,W2,6) by it in place.  codes or keep
  * may be NULL (mask only / zero-fill only is not allowed: keep NULL means the
- * mask is not stored). */
+ * mask is not stored).  TOK_DROP_SIMILARITY is rejected (TOK_EINVAL): it
+ * needs scratch memory, use tok_select_similar. */
 tok_status tok_drop(const tok_drop_desc* drop, float* codes, uint8_t* keep, int N, int T2,
                     int H2, int W2, hipStream_t stream);
+
+/* Similarity-based token selection (Sec. 4.3, Eq. 3).  Latent frame 0 of each
+ * clip is its I-frame token matrix and is never dropped; the token of a later
+ * (P) frame at (h, w) scores the cosine similarity of its FSQ code vector to
+ * the I token at (h, w) (0 when either vector is zero).  Per clip, the
+ * D = min(ceil(rate * N_P), N_P) most similar of the N_P = (T2-1) H2 W2 P
+ * tokens are dropped, rate clamped to [0, 1]: the similarity threshold of
+ * Sec. 4.3 is set by the bandwidth budget as a drop count.  Equal similarities
+ * go to the lower token index i = (t H2 + h) W2 + w first, so the result is
+ * unique.  Similarities are compared exactly (codes * 4 are integers, the
+ * comparison is of rationals, not of rounded cosines).
+ * codes: device float32 (N,T2,H2,W2,6), dropped tokens zero-filled in place.
+ * keep: device uint8 (N,T2,H2,W2) output or NULL.  ws: device scratch of at
+ * least tok_select_workspace_size bytes; its contents are not preserved.
+ * Errors: TOK_EINVAL (null codes / ws), TOK_ESHAPE (N > 65535 or a clip of
+ * 2^31 tokens or more), TOK_EWORKSPACE. */
+tok_status tok_select_workspace_size(int N, int T2, int H2, int W2, size_t* bytes);
+tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, int T2, int H2,
+                              int W2, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Decoder g_theta: codes float32 (N,T2,H2,W2,6) -> x_hat float32
  * (N, 4(T2-1)+1, 4 H2, 4 W2, 3). */
@@ -159,7 +184,8 @@ tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H
  * projection kernels), 16 GroupNorm finalize, 17 GroupNorm apply + SiLU,
  * and for tok_train_forward / tok_backward: 18 adjoint (input-gradient)
  * convolutions, 19 weight-gradient kernels, 20 GroupNorm+SiLU backward,
- * 21 other backward kernels; tok_kernel_name(k) names them.
+ * 21 other backward kernels, 22 similarity-based token selection (tok_encode
+ * with TOK_DROP_SIMILARITY); tok_kernel_name(k) names them.
  * Profiling allocates events and is meant for measurement runs; do not
  * profile one model from several host threads at once. */
 tok_status tok_profile_begin(tok_model* model);
@@ -249,7 +275,7 @@ typedef struct {
   int T, H, W;              /* clip shape (T % 4 == 1, H and W multiples of 4) */
   const uint8_t* pixels;    /* host (T,H,W,3) uint8; copied to the device at admission
                                (pinned memory makes the copy asynchronous) */
-  tok_drop_desc drop;       /* per-clip token drop (NONE, BERNOULLI or ROWS); clip_id0 is
+  tok_drop_desc drop;       /* per-clip token drop (NONE, BERNOULLI, ROWS or SIMILARITY); clip_id0 is
                                this clip's hash id */
 } tok_request;
 

@@ -347,7 +347,7 @@ def similarity_drop_count(rate, n_p):
 
 
 def similarity_keep(codes, rate):
-    """keep (N, T2, H2, W2) of similarity-based token selection (Sec. 5,
+    """keep (N, T2, H2, W2) of similarity-based token selection (Sec. 4.3,
     Eq. 3).  Latent frame 0 of a clip is the I-frame token matrix and is
     never dropped; every later latent frame is a P-frame matrix whose token
     at (h', w') is scored by its cosine similarity to the I token at the

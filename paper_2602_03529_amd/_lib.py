@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libtok.so")
 
 TOK_OK = 0
 TOK_F32, TOK_BF16, TOK_FP8_E4M3 = 0, 1, 2
-TOK_DROP_NONE, TOK_DROP_BERNOULLI, TOK_DROP_ROWS, TOK_DROP_EXTERNAL = 0, 1, 2, 3
+TOK_DROP_NONE, TOK_DROP_BERNOULLI, TOK_DROP_ROWS, TOK_DROP_EXTERNAL, TOK_DROP_SIMILARITY = 0, 1, 2, 3, 4
 TOK_WS_ENCODE, TOK_WS_DECODE, TOK_WS_ROUNDTRIP, TOK_WS_STREAM = 1, 2, 3, 16
 
 
@@ -66,6 +66,10 @@ def lib():
     L.tok_drop.restype = i32
     L.tok_drop.argtypes = [C.POINTER(DropDesc), vp, vp, i32, i32, i32, i32, vp]
     L.tok_decode.restype = i32
+    L.tok_select_workspace_size.restype = i32
+    L.tok_select_workspace_size.argtypes = [i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_select_similar.restype = i32
+    L.tok_select_similar.argtypes = [C.c_float, vp, vp, i32, i32, i32, i32, vp, sz, vp]
     L.tok_decode.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
     L.tok_model_set_weights.restype = i32
     L.tok_model_set_weights.argtypes = [vp, vp, vp]

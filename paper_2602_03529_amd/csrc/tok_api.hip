@@ -160,7 +160,7 @@ const char* kKernelNames[K_IDS] = {
     "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
     "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
     "dec.rb2.b", "dec.conv_out", "gn_finalize", "gn_silu", "bwd.dgrad", "bwd.wgrad", "bwd.gn_silu",
-    "bwd.other"};
+    "bwd.other", "select.similarity"};
 
 // Conv launch: reads the whole input buffer `iw` (its frames are addressed
 // through their global numbers) and writes the window `ow` of the output.
@@ -303,13 +303,25 @@ ChunkWins chunk_windows(const Plan& p, int L0, int L1) {
 }
 
 bool valid_drop(const tok_drop_desc* dd) {
-  return !dd || (dd->mode >= 0 && dd->mode <= 3 && (dd->mode != TOK_DROP_EXTERNAL || dd->ext_keep));
+  return !dd || (dd->mode >= 0 && dd->mode <= TOK_DROP_SIMILARITY && (dd->mode != TOK_DROP_EXTERNAL || dd->ext_keep));
+}
+
+bool is_similarity(const tok_drop_desc* dd) { return dd && dd->mode == TOK_DROP_SIMILARITY; }
+
+// Drop count of the similarity selection: min(ceil(rate * n_p), n_p), rate
+// clamped to [0, 1] (NaN counts as 0), evaluated in double.
+long long similarity_drop_count(float rate, long long n_p) {
+  double r = rate;
+  if (!(r >= 0.0)) r = 0.0;
+  if (r > 1.0) r = 1.0;
+  const long long d = (long long)std::ceil(r * (double)n_p);
+  return d < n_p ? d : n_p;
 }
 
 DropArgs make_drop(const tok_drop_desc* dd) {
   DropArgs a;
   std::memset(&a, 0, sizeof(a));
-  if (!dd) return a;
+  if (!dd || dd->mode == TOK_DROP_SIMILARITY) return a;  // selected after FSQ, not per token
   a.mode = dd->mode;
   double r = dd->rate;
   if (!(r >= 0.0)) r = 0.0;
@@ -631,6 +643,7 @@ tok_status tok_workspace_size(const tok_model* m, int N, int T, int H, int W, in
     return TOK_OK;
   }
   *bytes = make_plan(d, m->prec, (what & TOK_WS_STREAM) ? 1 : d.T2).total;
+  if (kind & TOK_WS_ENCODE) *bytes = std::max(*bytes, similarity_ws_bytes(N, d.T2, d.H2, d.W2));
   return TOK_OK;
 }
 
@@ -645,6 +658,13 @@ tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))
     return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
+  if (is_similarity(drop)) {
+    if (!codes) return fail(TOK_EINVAL, "similarity-based selection needs the codes output");
+    if (ws_bytes < similarity_ws_bytes(N, d.T2, d.H2, d.W2))
+      return fail(TOK_EWORKSPACE, "workspace too small for the similarity selection");
+    if ((long long)d.T2 * d.H2 * d.W2 > 0x7fffffffLL || N > 65535)
+      return fail(TOK_ESHAPE, "similarity selection needs N <= 65535 and under 2^31 tokens per clip");
+  }
   Ws w{static_cast<char*>(ws), p};
   const FsqConst fc = make_fsq_const();
   const DropArgs da = make_drop(drop);
@@ -673,6 +693,12 @@ tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W
       TOK_TRY(shift_cache(w.l1(), c.l1, N, f1b, kCache1, s));
     }
   }
+  if (is_similarity(drop)) {
+    // the activations are dead: the selection reuses the workspace from its start
+    Timed tm(m, K_SELECT, s);
+    TOK_HIP(launch_similarity_drop(codes, keep, N, d.T2, d.H2, d.W2,
+                                   similarity_drop_count(drop->rate, (long long)(d.T2 - 1) * d.H2 * d.W2), ws, s));
+  }
   return TOK_OK;
 }
 
@@ -686,9 +712,30 @@ tok_status tok_quantize(const float* z, size_t n_tokens, float* codes, int32_t* 
 tok_status tok_drop(const tok_drop_desc* drop, float* codes, uint8_t* keep, int N, int T2, int H2, int W2,
                     hipStream_t s) {
   if (!drop || !valid_drop(drop)) return fail(TOK_EINVAL, "bad drop descriptor");
+  if (is_similarity(drop)) return fail(TOK_EINVAL, "similarity-based selection needs scratch: tok_select_similar");
   if (N < 1 || T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
   if (!codes && !keep) return TOK_OK;
   TOK_HIP(launch_drop(make_drop(drop), codes, keep, N, T2, H2, W2, s));
+  return TOK_OK;
+}
+
+tok_status tok_select_workspace_size(int N, int T2, int H2, int W2, size_t* bytes) {
+  if (!bytes) return fail(TOK_EINVAL, "null argument");
+  if (N < 1 || T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
+  *bytes = similarity_ws_bytes(N, T2, H2, W2);
+  return TOK_OK;
+}
+
+tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, int T2, int H2, int W2, void* ws,
+                              size_t ws_bytes, hipStream_t s) {
+  if (!codes || !ws) return fail(TOK_EINVAL, "null argument");
+  if (N < 1 || T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
+  if (N > 65535 || (long long)T2 * H2 * W2 > 0x7fffffffLL)
+    return fail(TOK_ESHAPE, "need N <= 65535 and under 2^31 tokens per clip");
+  if (ws_bytes < similarity_ws_bytes(N, T2, H2, W2)) return fail(TOK_EWORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(codes) & 7) return fail(TOK_EINVAL, "codes must be 8-byte aligned");
+  TOK_HIP(launch_similarity_drop(codes, keep, N, T2, H2, W2,
+                                 similarity_drop_count(rate, (long long)(T2 - 1) * H2 * W2), ws, s));
   return TOK_OK;
 }
 

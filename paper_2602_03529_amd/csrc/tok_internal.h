@@ -164,6 +164,13 @@ hipError_t launch_quantize(const float* z, size_t n, const FsqConst& fc, float* 
                            int32_t* idx, hipStream_t s);
 hipError_t launch_drop(const DropArgs& d, float* codes, uint8_t* keep, int N, int T2, int H2,
                        int W2, hipStream_t s);
+// Similarity-based token selection (Sec. 4.3, Eq. 3): drops the D P tokens of
+// each clip most similar to the co-located I token (ties to the lower index)
+// from codes (N, T2, H2, W2, 6) in place and writes keep (or NULL).  ws holds
+// similarity_ws_bytes(N, T2, H2, W2) bytes (unused when D is 0 or every P token).
+size_t similarity_ws_bytes(int N, int T2, int H2, int W2);
+hipError_t launch_similarity_drop(float* codes, uint8_t* keep, int N, int T2, int H2, int W2, long long D, void* ws,
+                                  hipStream_t s);
 // 1x1x1 projection 6 -> 128: latent frames [t0, t0+F) of dense codes
 // (N, T2, HW, 6) into buffer frames [f0, f0+F) of chunked activations with Tb
 // frames per clip.

@@ -193,7 +193,11 @@ struct tok_server {
     for (int i = 0; i < n; ++i) {
       tok_drop_desc d = b->reqs[i]->req.drop;
       d.ext_keep = nullptr;
-      e = tok_drop(&d, codes + (size_t)i * s.tok * 6, keep + (size_t)i * s.tok, 1, s.T2, s.H2, s.W2, st);
+      float* ci = codes + (size_t)i * s.tok * 6;
+      uint8_t* ki = keep + (size_t)i * s.tok;
+      // the selection's scratch is the batch workspace, idle between encode and decode
+      e = d.mode == TOK_DROP_SIMILARITY ? tok_select_similar(d.rate, ci, ki, 1, s.T2, s.H2, s.W2, ws, wsb, st)
+                                         : tok_drop(&d, ci, ki, 1, s.T2, s.H2, s.W2, st);
       if (e != TOK_OK) return e;
     }
     e = tok_decode(model, codes, n, s.T2, s.H2, s.W2, xhat, ws, wsb, st);
@@ -375,7 +379,9 @@ tok_status tok_server_submit(tok_server* sv, const tok_request* req, uint64_t* t
   if (!sv || !req || !req->pixels || !ticket) return TOK_EINVAL;
   Shape s;
   if (!make_shape(req->T, req->H, req->W, &s)) return TOK_ESHAPE;
-  if (req->drop.mode < TOK_DROP_NONE || req->drop.mode > TOK_DROP_ROWS) return TOK_EINVAL;  // no external masks
+  // no external masks (the request does not outlive its pixels' upload)
+  if (req->drop.mode < TOK_DROP_NONE || req->drop.mode > TOK_DROP_SIMILARITY || req->drop.mode == TOK_DROP_EXTERNAL)
+    return TOK_EINVAL;
   Request* r = new Request;
   r->req = *req;
   r->shape = s;

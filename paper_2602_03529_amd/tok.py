@@ -230,7 +230,7 @@ def tokenizer_loss(model: "TokModel", params: torch.Tensor, x: torch.Tensor, kee
     return TokenizerLoss.apply(params, model, x, keep)
 
 
-KERNEL_IDS = 22
+KERNEL_IDS = 23
 
 
 class Profile:
@@ -277,6 +277,26 @@ def drop(codes: torch.Tensor | None, d: Drop, shape=None, keep=True):
     kp = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None
     desc = d.desc()
     L.check("tok_drop", L.lib().tok_drop(C.byref(desc), _ptr(codes), _ptr(kp), N, T2, H2, W2, _stream(dev)))
+    return kp
+
+
+def select_workspace_size(N: int, T2: int, H2: int, W2: int) -> int:
+    b = C.c_size_t()
+    L.check("tok_select_workspace_size", L.lib().tok_select_workspace_size(N, T2, H2, W2, C.byref(b)))
+    return int(b.value)
+
+
+def select_similar(codes: torch.Tensor, rate: float, keep=True, ws=None):
+    """Similarity-based token selection (Sec. 4.3, Eq. 3) on codes
+    (N,T2,H2,W2,6) in place; returns keep (N,T2,H2,W2) uint8 or None."""
+    N, T2, H2, W2, _ = codes.shape
+    _need(codes, torch.float32, (N, T2, H2, W2, 6), "codes")
+    dev = codes.device
+    kp = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None
+    if ws is None:
+        ws = torch.empty(select_workspace_size(N, T2, H2, W2), dtype=torch.uint8, device=dev)
+    L.check("tok_select_similar", L.lib().tok_select_similar(float(rate), _ptr(codes), _ptr(kp), N, T2, H2, W2,
+                                                             _ptr(ws), ws.numel(), _stream(dev)))
     return kp
 
 

@@ -81,6 +81,11 @@ tok_status tok_drop(const tok_drop_desc*, float*, uint8_t* keep, int N, int T2, 
   if (keep) std::memset(keep, 1, (size_t)N * T2 * H2 * W2);
   return TOK_OK;
 }
+tok_status tok_select_similar(float, float*, uint8_t* keep, int N, int T2, int H2, int W2, void*, size_t,
+                              hipStream_t) {
+  if (keep) std::memset(keep, 1, (size_t)N * T2 * H2 * W2);
+  return TOK_OK;
+}
 tok_status tok_decode(tok_model*, const float* codes, int N, int T2, int H2, int W2, float* xhat, void*, size_t,
                       hipStream_t) {
   const size_t tok = (size_t)T2 * H2 * W2;

@@ -1,4 +1,4 @@
-"""Pins of the oracle's similarity-based token selection (Sec. 5, Eq. 3):
+"""Pins of the oracle's similarity-based token selection (Sec. 4.3, Eq. 3):
 brute force with float64 cosines, exact ties between different integer
 vectors, zero norms, the drop count, the I frame, and degenerate rates."""
 import math
