@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tokenizer encode+decode frames/s at 720p, BF16 vs FP32, ≤0.5 dB PSNR vs oracle"
 BF16_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Mean HBM bytes per launch of the level-0 residual-block conv at 4 x 17 x
 # 1280x720 BF16, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled
 # by the same counters on a 1 GiB device copy; see profiles/.  Valid for that
@@ -183,6 +184,83 @@ def fp8_leg(tok, wflat, dev, args):
     return out
 
 
+def coding_leg(tok, x, xhat, codes, idx, args):
+    """The coding steps around the tokenizer on the headline batch's own
+    tensors: similarity-based token selection (Sec. 4.3, Eq. 3) on its codes,
+    row packets and reassembly (Sec. 6.2), the pixel-residual layer (Sec. 4.3,
+    Eq. 4) on its clips and reconstructions, GoP-boundary blending (Sec. 4.2,
+    Eq. 2).  Per op: time per call (HIP events on the launching stream) and
+    algorithmic bytes / time against the 8 TB/s HBM peak (all are HBM- or
+    launch-bound)."""
+    import torch
+    s = torch.cuda.current_stream()
+
+    def timed_op(fn, pre=None, iters=10):
+        for _ in range(2):
+            if pre:
+                pre()
+            fn()
+        torch.cuda.synchronize()
+        tot = 0.0
+        for _ in range(iters):
+            if pre:
+                pre()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        return tot / iters
+
+    def entry(ms, alg, **kw):
+        gbs = alg / (ms / 1e3) / 1e9
+        return dict(us_per_call=round(ms * 1e3, 1), algorithmic_bytes=int(alg), gb_per_s=round(gbs, 1),
+                    frac_of_hbm_peak=round(gbs / HBM_PEAK_GBS, 4), **kw)
+
+    N, T2, H2, W2, _ = codes.shape
+    _, T, H, W, _ = x.shape
+    tokens = N * T2 * H2 * W2
+    out = {}
+    work = codes.clone()
+    ws = torch.empty(tok.select_workspace_size(N, T2, H2, W2), dtype=torch.uint8, device=codes.device)
+    keep = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=codes.device)
+    L = tok.L
+    lib = L.lib()
+    rate = args.select_rate
+
+    def select():
+        L.check("tok_select_similar", lib.tok_select_similar(
+            float(rate), work.data_ptr(), keep.data_ptr(), N, T2, H2, W2, ws.data_ptr(), ws.numel(), s.cuda_stream))
+    ms = timed_op(select, pre=lambda: work.copy_(codes))
+    dropped = int((keep == 0).sum())
+    out["select_similar"] = entry(ms, tokens * 25 + dropped * 24, rate=rate, dropped=dropped,
+                                  note="10 launches (keys, 8 radix passes, apply): launch-bound")
+    buf, offs = tok.packetize(idx, keep)
+    ms = timed_op(lambda: tok.packetize(idx, keep))
+    nbytes = int(offs[-1])
+    out["packetize"] = entry(ms, tokens * 5 + nbytes + 8 * (N * T2 * H2 + 1), stream_bytes=nbytes,
+                             bits_per_kept_token=round(8.0 * nbytes / max(tokens - dropped, 1), 2))
+    sel = offs[:-1].contiguous()
+    ms = timed_op(lambda: tok.reassemble(buf, sel, (N, T2, H2, W2)))
+    out["reassemble"] = entry(ms, nbytes + tokens * 25)
+    theta = args.residual_theta
+    res = tok.residual_compress(x, xhat, theta)
+    nnz = int(res["clip_offsets"][-1])
+    ms = timed_op(lambda: tok.residual_compress(x, xhat, theta))
+    px = N * H * W * 3
+    out["residual_compress"] = entry(ms, px * T * 5 + px * 4 + nnz * 8, theta=theta, nonzero=nnz,
+                                     note="untrained stand-in weights: the residual is dense")
+    r = res["r"]
+    ms = timed_op(lambda: tok.residual_apply(r, xhat))
+    out["residual_apply"] = entry(ms, px * 4 + px * T * 8)
+    prev = xhat.clone()
+    ms = timed_op(lambda: tok.gop_blend(prev, xhat, 2))
+    out["gop_blend_n2"] = entry(ms, px * 2 * 12)
+    out["workload"] = "the headline batch: latents %dx%dx%dx%d, clips %dx%dx%dx%d" % (N, T2, H2, W2, N, T, H, W)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +279,9 @@ def main():
     ap.add_argument("--fp8-steps", type=int, default=3,
                     help="timed decode steps of the fp8 leg (bf16 the same, f32 one); 0 skips it")
     ap.add_argument("--fp8-shape", type=str, default="2x33x1080x1920", help="NxTxHxW of the decode-only fp8 leg")
+    ap.add_argument("--coding", type=int, default=1, help="1: time the coding steps on the headline batch")
+    ap.add_argument("--select-rate", type=float, default=0.3, help="drop rate of the similarity selection leg")
+    ap.add_argument("--residual-theta", type=float, default=0.03, help="residual threshold of the coding leg")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -301,6 +382,14 @@ def main():
                     share_of_step=round(rb_ms / args.steps / ms_b, 3))
     total_flops = algorithmic_flops(N, T, H, W)
 
+    # ---- coding steps on the headline batch's tensors -----------------------
+    coding = None
+    if args.coding:
+        enc = mb.encode(x, z=False, keep=False)
+        coding = coding_leg(tok, x, xh_b, enc["codes"], enc["idx"], args)
+        del enc
+        print("bench: coding leg done", file=sys.stderr, flush=True)
+
     # ---- FP32 path on the same GPU -----------------------------------------
     fp32 = None
     if args.fp32_steps > 0:
@@ -372,7 +461,7 @@ def main():
                             batch=N, frames=T, height=H, width=W, precision="bf16"),
                 algorithmic_tflops_per_step=round(total_flops / 1e12, 3),
                 achieved_tflops=round(total_flops / (ms_b / 1e3) / 1e12, 2),
-                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, train=train, fp8=fp8,
+                roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, train=train, fp8=fp8, coding=coding,
                 per_kernel=per_kernel)
     print(json.dumps(line), flush=True)
 

@@ -168,6 +168,76 @@ tok_status tok_select_workspace_size(int N, int T2, int H2, int W2, size_t* byte
 tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, int T2, int H2,
                               int W2, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- Token packets (Sec. 6.2) --------------------------------------------
+ * The token matrices are sent row by row, one packet per row: a header with
+ * the row number and a mask of the row's valid (not dropped) tokens, then the
+ * valid tokens.  Rows of a batch are numbered g = (n T2 + t) H2 + h (for one
+ * clip, the row of its token matrices).  Wire format, little-endian, every
+ * field 4-byte aligned:
+ *   u32 g
+ *   u8  mask[ceil(W2/8)]   bit (w & 7) of byte (w >> 3) = 1: column w is valid
+ *   u8  0 ...              padding to a multiple of 4 bytes
+ *   u16 idx[count]         FSQ code index (< 64000) of each valid token, by column
+ *   u16 0                  present when count is odd
+ * Packets follow each other in row order with no gaps; every row gets a
+ * packet, also one with no valid token. */
+
+/* Upper bound of the stream length: every token valid. */
+tok_status tok_packets_max_bytes(int N, int T2, int H2, int W2, size_t* bytes);
+
+/* Sender.  idx: device int32 (N,T2,H2,W2) FSQ indices (tok_encode's idx).
+ * keep: device uint8 (N,T2,H2,W2) mask, or NULL for all valid.  out: device
+ * buffer, 4-byte aligned, of out_bytes >= tok_packets_max_bytes bytes.
+ * offsets: device uint64 [N T2 H2 + 1], receives each packet's byte offset in
+ * out and, last, the stream's length.  Errors: TOK_EINVAL (null / misaligned
+ * pointer), TOK_ESHAPE, TOK_EWORKSPACE (out too small). */
+tok_status tok_packetize(const int32_t* idx, const uint8_t* keep, int N, int T2, int H2, int W2,
+                         uint8_t* out, size_t out_bytes, uint64_t* offsets, hipStream_t stream);
+
+/* Receiver.  buf: device bytes [bytes] holding the packets that arrived;
+ * offsets: device uint64 [n_packets], where each starts in buf (any order).
+ * codes: device float32 (N,T2,H2,W2,6), 8-byte aligned: every token is the
+ * zero code vector except the valid tokens of the packets, which get the
+ * code of their index.  keep: device uint8 (N,T2,H2,W2) or NULL: 1 exactly
+ * at the tokens a packet delivered.  A packet whose row number is not below
+ * N T2 H2 or which does not fit inside buf is skipped; a row must arrive at
+ * most once (or its copies must be identical).  A lost packet and a row of
+ * dropped tokens thus reach the decoder alike. */
+tok_status tok_reassemble(const uint8_t* buf, size_t bytes, const uint64_t* offsets,
+                          size_t n_packets, int N, int T2, int H2, int W2, float* codes,
+                          uint8_t* keep, hipStream_t stream);
+
+/* ---- Pixel residuals (Sec. 4.3, Eq. 4) -----------------------------------
+ * Sender: x uint8 (N,T,H,W,3) clips (16-byte aligned), xhat float32
+ * (N,T,H,W,3) their reconstructions (16-byte aligned), the averaging window
+ * being a clip's T frames.  r: float32 (N,H,W,3) out, 16-byte aligned:
+ * (1/T) sum_t (x_t/127.5 - 1 - xhat_t), sums in fp32 in frame order, with
+ * every entry of magnitude below theta set to 0.  The non-zero entries of r
+ * as a sparse list, clip by clip, each in increasing flat index
+ * (h W + w) 3 + c: index (uint32) and value (float32) arrays of `capacity`
+ * entries (entries past it are not written), clip_offsets uint64 [N + 1]:
+ * clip n's entries are [clip_offsets[n], clip_offsets[n+1]) (the total may
+ * exceed capacity; N H W 3 entries always fit).  ws: device scratch of
+ * tok_residual_workspace_size bytes.  Needs H, W multiples of 4 and
+ * N H W 3 < 2^32. */
+tok_status tok_residual_workspace_size(int N, int H, int W, size_t* bytes);
+tok_status tok_residual_compress(const uint8_t* x, const float* xhat, int N, int T, int H, int W,
+                                 float theta, float* r, uint32_t* index, float* value,
+                                 size_t capacity, uint64_t* clip_offsets, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+/* Receiver: xhat (N,T,H,W,3) += r (N,H,W,3) for every frame, in place. */
+tok_status tok_residual_apply(const float* r, float* xhat, int N, int T, int H, int W,
+                              hipStream_t stream);
+
+/* ---- GoP-boundary blending (Sec. 4.2, Eq. 2) -----------------------------
+ * xhat (N,T,H,W,3) is the current GoP's reconstruction, prev (N,T_prev,H,W,3)
+ * the previous GoP's.  In place, frame i = 1..n (1-based) of xhat becomes
+ * a_i prev[T_prev - n + i] + (1 - a_i) xhat[i] with a_i = (n - i) / n, in
+ * fp32; later frames are untouched.  Needs 1 <= n <= T, T_prev; both buffers
+ * 16-byte aligned. */
+tok_status tok_gop_blend(const float* prev, int T_prev, float* xhat, int N, int T, int H, int W,
+                         int n, hipStream_t stream);
+
 /* Decoder g_theta: codes float32 (N,T2,H2,W2,6) -> x_hat float32
  * (N, 4(T2-1)+1, 4 H2, 4 W2, 3). */
 tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H2, int W2,

@@ -70,6 +70,20 @@ def lib():
     L.tok_select_workspace_size.argtypes = [i32, i32, i32, i32, C.POINTER(sz)]
     L.tok_select_similar.restype = i32
     L.tok_select_similar.argtypes = [C.c_float, vp, vp, i32, i32, i32, i32, vp, sz, vp]
+    L.tok_packets_max_bytes.restype = i32
+    L.tok_packets_max_bytes.argtypes = [i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_packetize.restype = i32
+    L.tok_packetize.argtypes = [vp, vp, i32, i32, i32, i32, vp, sz, vp, vp]
+    L.tok_reassemble.restype = i32
+    L.tok_reassemble.argtypes = [vp, sz, vp, sz, i32, i32, i32, i32, vp, vp, vp]
+    L.tok_residual_workspace_size.restype = i32
+    L.tok_residual_workspace_size.argtypes = [i32, i32, i32, C.POINTER(sz)]
+    L.tok_residual_compress.restype = i32
+    L.tok_residual_compress.argtypes = [vp, vp, i32, i32, i32, i32, C.c_float, vp, vp, vp, sz, vp, vp, sz, vp]
+    L.tok_residual_apply.restype = i32
+    L.tok_residual_apply.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+    L.tok_gop_blend.restype = i32
+    L.tok_gop_blend.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, vp]
     L.tok_decode.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
     L.tok_model_set_weights.restype = i32
     L.tok_model_set_weights.argtypes = [vp, vp, vp]

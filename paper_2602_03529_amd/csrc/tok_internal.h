@@ -169,6 +169,22 @@ hipError_t launch_drop(const DropArgs& d, float* codes, uint8_t* keep, int N, in
 // from codes (N, T2, H2, W2, 6) in place and writes keep (or NULL).  ws holds
 // similarity_ws_bytes(N, T2, H2, W2) bytes (unused when D is 0 or every P token).
 size_t similarity_ws_bytes(int N, int T2, int H2, int W2);
+// Row packets of Sec. 6.2 (format in packets.hip): the sender writes packet
+// offsets[g] .. offsets[g+1] of every row g and offsets[G] = stream length;
+// the receiver zero-fills codes / keep and scatters the packets at offsets.
+long long packets_max_bytes(int N, int T2, int H2, int W2);
+hipError_t launch_packetize(const int32_t* idx, const uint8_t* keep, int N, int T2, int H2, int W2, uint8_t* out,
+                            unsigned long long* offsets, hipStream_t s);
+hipError_t launch_reassemble(const uint8_t* buf, unsigned long long bytes, const unsigned long long* offsets,
+                             long long n_packets, int N, int T2, int H2, int W2, float* codes, uint8_t* keep,
+                             hipStream_t s);
+// Pixel residuals (Sec. 4.3, Eq. 4) and GoP blending (Sec. 4.2, Eq. 2), see enhance.hip.
+size_t residual_ws_bytes(int N, int H, int W);
+hipError_t launch_residual(const uint8_t* x, const float* xhat, int N, int T, int H, int W, float theta, float* rs,
+                           uint32_t* index, float* value, long long capacity, unsigned long long* clip_off,
+                           void* ws, hipStream_t s);
+hipError_t launch_residual_apply(const float* rs, float* xhat, int N, int T, int H, int W, hipStream_t s);
+hipError_t launch_blend(const float* prev, int Tp, float* cur, int N, int T, int H, int W, int nb, hipStream_t s);
 hipError_t launch_similarity_drop(float* codes, uint8_t* keep, int N, int T2, int H2, int W2, long long D, void* ws,
                                   hipStream_t s);
 // 1x1x1 projection 6 -> 128: latent frames [t0, t0+F) of dense codes

@@ -6,11 +6,13 @@
 // ties going to the lower token index.  The selection is an exact top-D over
 // unique 64-bit keys, (similarity order key << 32) | (2^32 - 1 - token index),
 // done as a radix select with 8-bit digits from the top:
-//   sel_key_kernel    one 32-bit similarity key per P token, clears counters
+//   sel_key_kernel    one 32-bit similarity key per P token, clears the histograms
 //   sel_pass_kernel   x8: histogram of the next digit among the tokens that
-//                     match the digits chosen so far; the workgroup that
-//                     finishes a clip's histogram last picks that clip's digit
+//                     match the digits chosen so far; each workgroup first
+//                     derives the previous pass's digit from its histogram
 //   sel_apply_kernel  keep mask and zero fill against the D-th largest key
+// No workgroup waits for another and no device-scope fence is needed: a
+// histogram is read only by launches after the one that built it.
 // Every count is an integer, so the result does not depend on the order in
 // which workgroups run.
 #include "tok_internal.h"
@@ -35,7 +37,7 @@ struct SelState {
 struct SelWs {
   uint32_t* keys;  // [N][NP] similarity keys of the P tokens
   uint32_t* hist;  // [N][8][256] digit histograms
-  uint32_t* done;  // [N][8] finished workgroups per pass
+  SelState* st0;   // [N] state before pass 0 (need = D)
   SelState* st;    // [N][8] selection state after each pass
 };
 
@@ -49,7 +51,7 @@ SelWs carve(void* ws, int N, long long NP) {
   SelWs w;
   w.keys = reinterpret_cast<uint32_t*>(take((size_t)N * NP * 4));
   w.hist = reinterpret_cast<uint32_t*>(take((size_t)N * kSelPasses * 256 * 4));
-  w.done = reinterpret_cast<uint32_t*>(take((size_t)N * kSelPasses * 4));
+  w.st0 = reinterpret_cast<SelState*>(take((size_t)N * sizeof(SelState)));
   w.st = reinterpret_cast<SelState*>(take((size_t)N * kSelPasses * sizeof(SelState)));
   return w;
 }
@@ -84,14 +86,15 @@ __device__ __forceinline__ uint64_t composite(uint32_t key, long long token) {
   return ((uint64_t)key << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)token);
 }
 
-// grid (ceil(NP / 1024), N).  Workgroup 0 of a clip also clears its counters
-// (the pass kernels run after this one on the same stream).
+// grid (ceil(NP / 1024), N).  Workgroup 0 of a clip also clears its
+// histograms and sets the initial selection state (the pass kernels run after
+// this one on the same stream).
 __global__ void __launch_bounds__(kSelThreads) sel_key_kernel(const float* __restrict__ codes, SelWs w, int T2,
-                                                               int HW, long long NP) {
+                                                               int HW, long long NP, unsigned D) {
   const int n = blockIdx.y, tid = threadIdx.x;
   if (blockIdx.x == 0) {
     for (int b = tid; b < kSelPasses * 256; b += kSelThreads) w.hist[(size_t)n * kSelPasses * 256 + b] = 0;
-    if (tid < kSelPasses) w.done[n * kSelPasses + tid] = 0;
+    if (tid == 0) w.st0[n] = SelState{0ull, D, 0u};
   }
   const float* clip = codes + (size_t)n * T2 * HW * 6;
 #pragma unroll
@@ -120,21 +123,63 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* hist, bool cand, unsigne
   }
 }
 
-// grid (ceil(NP / kSelTile), N).
-__global__ void __launch_bounds__(kSelThreads) sel_pass_kernel(SelWs w, long long NP, int HW, int pass,
-                                                                unsigned D) {
+// Selection state after pass `pass` of clip n, from the state after the
+// previous pass and that pass's finished histogram (wave 0 of the calling
+// workgroup; lane 0 returns it).  Lane l holds bins 255-4l .. 252-4l
+// (highest first); the digit is the bin where the running count from the top
+// first reaches `need` (the candidates number at least `need`, so one does).
+__device__ SelState next_state(const SelWs& w, int n, int pass, int lane) {
+  const SelState prev = pass == 0 ? w.st0[n] : w.st[n * kSelPasses + pass - 1];
+  const uint32_t* hist = w.hist + ((size_t)n * kSelPasses + pass) * 256;
+  uint32_t c[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    c[q] = hist[255 - 4 * lane - q];
+    sum += c[q];
+  }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  const unsigned need = prev.need;
+  const unsigned long long m = __ballot(incl >= need);
+  const int L = __ffsll((long long)m) - 1;
+  uint32_t cum = incl - sum;
+  int q = 0;
+  for (; q < 3; ++q) {
+    if (cum + c[q] >= need) break;
+    cum += c[q];
+  }
+  SelState s;
+  s.prefix = (prev.prefix << 8) | (unsigned long long)(255 - 4 * lane - q);
+  s.need = need - cum;
+  s.pad = 0;
+  // broadcast lane L's result
+  s.prefix = __shfl(s.prefix, L, 64);
+  s.need = __shfl(s.need, L, 64);
+  return s;
+}
+
+// grid (ceil(NP / kSelTile), N).  Pass p > 0 first derives the digit of pass
+// p - 1 (every workgroup alike, from the histogram the previous launch
+// finished) and stores the state, identically from every workgroup, for the
+// next launch; no workgroup waits for another.
+__global__ void __launch_bounds__(kSelThreads) sel_pass_kernel(SelWs w, long long NP, int HW, int pass) {
   __shared__ uint32_t wh[kSelThreads / 64][256];
-  __shared__ int s_last;
+  __shared__ unsigned long long s_prefix;
   const int n = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int b = tid; b < (kSelThreads / 64) * 256; b += kSelThreads) (&wh[0][0])[b] = 0;
-  unsigned long long prefix = 0;
-  unsigned need = D;
-  if (pass > 0) {
-    const SelState s = w.st[n * kSelPasses + pass - 1];
-    prefix = s.prefix;
-    need = s.need;
+  if (pass > 0 && wv == 0) {
+    const SelState s = next_state(w, n, pass - 1, lane);
+    if (lane == 0) {
+      s_prefix = s.prefix;
+      w.st[n * kSelPasses + pass - 1] = s;
+    }
   }
   __syncthreads();
+  const unsigned long long prefix = pass > 0 ? s_prefix : 0ull;
   const int shift = 56 - 8 * pass;
   const int hs = pass == 0 ? 0 : shift + 8;  // the chosen digits sit above bit hs
   const uint32_t* keys = w.keys + (size_t)n * NP;
@@ -154,71 +199,44 @@ __global__ void __launch_bounds__(kSelThreads) sel_pass_kernel(SelWs w, long lon
   uint32_t tot = 0;
 #pragma unroll
   for (int q = 0; q < kSelThreads / 64; ++q) tot += wh[q][tid];
-  uint32_t* hist = w.hist + ((size_t)n * kSelPasses + pass) * 256;
-  if (tot) atomicAdd(&hist[tid], tot);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&w.done[n * kSelPasses + pass], 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!s_last || wv != 0) return;
-  __threadfence();
-  // Last workgroup of this clip: lane l holds bins 255-4l .. 252-4l (highest
-  // first); the digit is the bin where the running count from the top first
-  // reaches `need` (the candidates number at least `need`, so one does).
-  uint32_t c[4], sum = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    c[q] = __hip_atomic_load(&hist[255 - 4 * lane - q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sum += c[q];
-  }
-  uint32_t incl = sum;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += t;
-  }
-  const unsigned long long m = __ballot(incl >= need);
-  if (lane == __ffsll((long long)m) - 1) {
-    uint32_t cum = incl - sum;
-    int q = 0;
-    for (; q < 3; ++q) {
-      if (cum + c[q] >= need) break;
-      cum += c[q];
-    }
-    SelState s;
-    s.prefix = (prefix << 8) | (unsigned long long)(255 - 4 * lane - q);
-    s.need = need - cum;
-    s.pad = 0;
-    w.st[n * kSelPasses + pass] = s;
-  }
+  if (tot) atomicAdd(&w.hist[((size_t)n * kSelPasses + pass) * 256 + tid], tot);
 }
 
 enum { SEL_KEEP_ALL = 0, SEL_DROP_ALL_P = 1, SEL_THRESHOLD = 2 };
 
-// grid (ceil(T2 HW / 256), N): keep for every token of the clip, zero fill of
-// the dropped ones.  Latent frame 0 (the I frame) is always kept.
+// grid (ceil(T2 HW / 1024), N): keep for every token of the clip, zero fill of
+// the dropped ones, 4 tokens per thread.  Latent frame 0 (the I frame) is
+// always kept.
 __global__ void __launch_bounds__(kSelThreads) sel_apply_kernel(float* __restrict__ codes, uint8_t* __restrict__ keep,
                                                                  SelWs w, int T2, int HW, long long NP, int mode) {
-  const int n = blockIdx.y;
-  const long long i = (long long)blockIdx.x * kSelThreads + threadIdx.x;
-  const long long per = (long long)T2 * HW;
-  if (i >= per) return;
-  bool drop = false;
-  if (i >= HW) {
-    if (mode == SEL_DROP_ALL_P) {
-      drop = true;
-    } else if (mode == SEL_THRESHOLD) {
-      const unsigned long long thr = w.st[n * kSelPasses + kSelPasses - 1].prefix;
-      drop = composite(w.keys[(size_t)n * NP + (i - HW)], i) >= thr;
+  __shared__ unsigned long long s_thr;
+  const int n = blockIdx.y, tid = threadIdx.x;
+  if (mode == SEL_THRESHOLD) {
+    // the D-th largest key: the digits of the first 7 passes and the last pass's histogram
+    if (tid < 64) {
+      const SelState s = next_state(w, n, kSelPasses - 1, tid);
+      if (tid == 0) s_thr = s.prefix;
     }
+    __syncthreads();
   }
-  if (keep) keep[(size_t)n * per + i] = drop ? 0 : 1;
-  if (drop) {
-    float2* c2 = reinterpret_cast<float2*>(codes + ((size_t)n * per + i) * 6);
-    const float2 z = make_float2(0.f, 0.f);
-    c2[0] = z;
-    c2[1] = z;
-    c2[2] = z;
+  const long long per = (long long)T2 * HW;
+#pragma unroll
+  for (int k = 0; k < kSelKeyItems; ++k) {
+    const long long i = ((long long)blockIdx.x * kSelKeyItems + k) * kSelThreads + tid;
+    if (i >= per) break;
+    bool drop = false;
+    if (i >= HW) {
+      if (mode == SEL_DROP_ALL_P) drop = true;
+      else if (mode == SEL_THRESHOLD) drop = composite(w.keys[(size_t)n * NP + (i - HW)], i) >= s_thr;
+    }
+    if (keep) keep[(size_t)n * per + i] = drop ? 0 : 1;
+    if (drop) {
+      float2* c2 = reinterpret_cast<float2*>(codes + ((size_t)n * per + i) * 6);
+      const float2 z = make_float2(0.f, 0.f);
+      c2[0] = z;
+      c2[1] = z;
+      c2[2] = z;
+    }
   }
 }
 
@@ -227,7 +245,7 @@ __global__ void __launch_bounds__(kSelThreads) sel_apply_kernel(float* __restric
 size_t similarity_ws_bytes(int N, int T2, int H2, int W2) {
   const long long NP = (long long)(T2 - 1) * H2 * W2;
   auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return a((size_t)N * NP * 4) + a((size_t)N * kSelPasses * 256 * 4) + a((size_t)N * kSelPasses * 4) +
+  return a((size_t)N * NP * 4) + a((size_t)N * kSelPasses * 256 * 4) + a((size_t)N * sizeof(SelState)) +
          a((size_t)N * kSelPasses * sizeof(SelState));
 }
 
@@ -245,13 +263,13 @@ hipError_t launch_similarity_drop(float* codes, uint8_t* keep, int N, int T2, in
     if (!ws) return hipErrorInvalidValue;
     w = carve(ws, N, NP);
     const long long kg = (NP + kSelKeyItems * kSelThreads - 1) / (kSelKeyItems * kSelThreads);
-    hipLaunchKernelGGL(sel_key_kernel, dim3((unsigned)kg, N), dim3(kSelThreads), 0, s, codes, w, T2, (int)HW, NP);
+    hipLaunchKernelGGL(sel_key_kernel, dim3((unsigned)kg, N), dim3(kSelThreads), 0, s, codes, w, T2, (int)HW, NP,
+                       (unsigned)D);
     const long long pg = (NP + kSelTile - 1) / kSelTile;
     for (int pass = 0; pass < kSelPasses; ++pass)
-      hipLaunchKernelGGL(sel_pass_kernel, dim3((unsigned)pg, N), dim3(kSelThreads), 0, s, w, NP, (int)HW, pass,
-                         (unsigned)D);
+      hipLaunchKernelGGL(sel_pass_kernel, dim3((unsigned)pg, N), dim3(kSelThreads), 0, s, w, NP, (int)HW, pass);
   }
-  const long long ag = ((long long)T2 * HW + kSelThreads - 1) / kSelThreads;
+  const long long ag = ((long long)T2 * HW + kSelKeyItems * kSelThreads - 1) / (kSelKeyItems * kSelThreads);
   hipLaunchKernelGGL(sel_apply_kernel, dim3((unsigned)ag, N), dim3(kSelThreads), 0, s, codes, keep, w, T2, (int)HW,
                      NP, mode);
   return hipGetLastError();

@@ -300,6 +300,82 @@ def select_similar(codes: torch.Tensor, rate: float, keep=True, ws=None):
     return kp
 
 
+def packetize(idx: torch.Tensor, keep: torch.Tensor | None = None):
+    """Row packets (Sec. 6.2) of FSQ indices (N,T2,H2,W2) int32 under keep:
+    returns (buf uint8 of the worst-case length, offsets uint64 [N T2 H2 + 1];
+    offsets[-1] is the stream's length)."""
+    N, T2, H2, W2 = idx.shape
+    _need(idx, torch.int32, (N, T2, H2, W2), "idx")
+    if keep is not None:
+        _need(keep, torch.uint8, (N, T2, H2, W2), "keep")
+    dev = idx.device
+    b = C.c_size_t()
+    L.check("tok_packets_max_bytes", L.lib().tok_packets_max_bytes(N, T2, H2, W2, C.byref(b)))
+    buf = torch.empty(int(b.value), dtype=torch.uint8, device=dev)
+    offs = torch.empty(N * T2 * H2 + 1, dtype=torch.uint64, device=dev)
+    L.check("tok_packetize", L.lib().tok_packetize(_ptr(idx), _ptr(keep), N, T2, H2, W2, _ptr(buf), buf.numel(),
+                                                   _ptr(offs), _stream(dev)))
+    return buf, offs
+
+
+def reassemble(buf: torch.Tensor, offsets: torch.Tensor, shape, keep=True, nbytes=None):
+    """Receiver (Sec. 6.2): codes (N,T2,H2,W2,6) float32 and keep from the
+    packets of buf starting at `offsets` (uint64, any order)."""
+    N, T2, H2, W2 = shape
+    dev = buf.device
+    assert buf.dtype == torch.uint8 and buf.is_contiguous()
+    assert offsets.dtype == torch.uint64 and offsets.is_contiguous() and offsets.device == dev
+    codes = torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=dev)
+    kp = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None
+    nb = buf.numel() if nbytes is None else int(nbytes)
+    L.check("tok_reassemble", L.lib().tok_reassemble(_ptr(buf), nb, _ptr(offsets), offsets.numel(), N, T2, H2, W2,
+                                                     _ptr(codes), _ptr(kp), _stream(dev)))
+    return codes, kp
+
+
+def residual_compress(x: torch.Tensor, xhat: torch.Tensor, theta: float, capacity=None, ws=None):
+    """Pixel residual layer (Sec. 4.3, Eq. 4): dict(r (N,H,W,3), index, value,
+    clip_offsets [N+1]) for clips x uint8 and reconstructions xhat float32."""
+    N, T, H, W, _ = x.shape
+    _need(x, torch.uint8, (N, T, H, W, 3), "x")
+    _need(xhat, torch.float32, (N, T, H, W, 3), "xhat")
+    dev = x.device
+    cap = N * H * W * 3 if capacity is None else int(capacity)
+    r = torch.empty((N, H, W, 3), dtype=torch.float32, device=dev)
+    index = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    value = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    co = torch.empty(N + 1, dtype=torch.uint64, device=dev)
+    if ws is None:
+        b = C.c_size_t()
+        L.check("tok_residual_workspace_size", L.lib().tok_residual_workspace_size(N, H, W, C.byref(b)))
+        ws = torch.empty(int(b.value), dtype=torch.uint8, device=dev)
+    L.check("tok_residual_compress", L.lib().tok_residual_compress(
+        _ptr(x), _ptr(xhat), N, T, H, W, float(theta), _ptr(r), _ptr(index), _ptr(value), cap, _ptr(co), _ptr(ws),
+        ws.numel(), _stream(dev)))
+    return dict(r=r, index=index, value=value, clip_offsets=co)
+
+
+def residual_apply(r: torch.Tensor, xhat: torch.Tensor):
+    """xhat (N,T,H,W,3) += r (N,H,W,3) for every frame, in place."""
+    N, T, H, W, _ = xhat.shape
+    _need(xhat, torch.float32, (N, T, H, W, 3), "xhat")
+    _need(r, torch.float32, (N, H, W, 3), "r")
+    L.check("tok_residual_apply", L.lib().tok_residual_apply(_ptr(r), _ptr(xhat), N, T, H, W, _stream(xhat.device)))
+    return xhat
+
+
+def gop_blend(prev: torch.Tensor, xhat: torch.Tensor, n: int = 2):
+    """GoP-boundary blending (Sec. 4.2, Eq. 2) of xhat's first n frames with
+    prev's last n, in place."""
+    N, T, H, W, _ = xhat.shape
+    _need(xhat, torch.float32, (N, T, H, W, 3), "xhat")
+    Tp = prev.shape[1]
+    _need(prev, torch.float32, (N, Tp, H, W, 3), "prev")
+    L.check("tok_gop_blend", L.lib().tok_gop_blend(_ptr(prev), Tp, _ptr(xhat), N, T, H, W, int(n),
+                                                   _stream(xhat.device)))
+    return xhat
+
+
 class TokServer:
     """tok_server: streaming request loop with continuous batching under an HBM budget."""
 

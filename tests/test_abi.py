@@ -30,7 +30,9 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for need in ["tok_encode", "tok_quantize", "tok_drop", "tok_decode", "tok_model_create",
-                 "tok_workspace_size", "tok_weight_count"]:
+                 "tok_workspace_size", "tok_weight_count", "tok_backward", "tok_select_similar",
+                 "tok_packetize", "tok_reassemble", "tok_residual_compress", "tok_residual_apply",
+                 "tok_gop_blend"]:
         assert need in names, names
 
 
