@@ -327,7 +327,7 @@ def reassemble(buf: torch.Tensor, offsets: torch.Tensor, shape, keep=True, nbyte
     assert offsets.dtype == torch.uint64 and offsets.is_contiguous() and offsets.device == dev
     codes = torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=dev)
     kp = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None
-    nb = buf.numel() if nbytes is None else int(nbytes)
+    nb = buf.numel() if nbytes is None else min(int(nbytes), buf.numel())
     L.check("tok_reassemble", L.lib().tok_reassemble(_ptr(buf), nb, _ptr(offsets), offsets.numel(), N, T2, H2, W2,
                                                      _ptr(codes), _ptr(kp), _stream(dev)))
     return codes, kp
