@@ -238,6 +238,17 @@ tok_status tok_residual_apply(const float* r, float* xhat, int N, int T, int H, 
 tok_status tok_gop_blend(const float* prev, int T_prev, float* xhat, int N, int T, int H, int W,
                          int n, hipStream_t stream);
 
+/* tok_decode with the same blend fused into C_out's epilogue: the decoded
+ * frames i = 1..n are written already blended with prev (N,T_prev,H,W,3,
+ * float32, device), the previous GoP's reconstruction, so a stream of GoPs
+ * is decoded and smoothed in one pass per GoP (overlapped-GoP streaming keeps
+ * the last n frames of each output as the next call's prev, T_prev = n).
+ * prev must not overlap xhat.  Errors as tok_decode, plus TOK_EINVAL for a
+ * null prev or n outside 1..min(T, T_prev). */
+tok_status tok_decode_blend(tok_model* model, const float* codes, int N, int T2, int H2, int W2,
+                            const float* prev, int T_prev, int n, float* xhat, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* Decoder g_theta: codes float32 (N,T2,H2,W2,6) -> x_hat float32
  * (N, 4(T2-1)+1, 4 H2, 4 W2, 3). */
 tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H2, int W2,

@@ -84,6 +84,8 @@ def lib():
     L.tok_residual_apply.argtypes = [vp, vp, i32, i32, i32, i32, vp]
     L.tok_gop_blend.restype = i32
     L.tok_gop_blend.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, vp]
+    L.tok_decode_blend.restype = i32
+    L.tok_decode_blend.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, sz, vp]
     L.tok_decode.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
     L.tok_model_set_weights.restype = i32
     L.tok_model_set_weights.argtypes = [vp, vp, vp]

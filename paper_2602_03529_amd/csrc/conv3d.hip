@@ -656,6 +656,15 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
         if (valid) {
           float* op = reinterpret_cast<float*>(a.out) +
                       (((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3;
+          if (a.blend_prev != nullptr && tg < a.blend_n) {
+            // frame i = tg + 1 of the GoP: a_i prev[Tp - n + i] + (1 - a_i) x_hat, a_i = (n - i) / n
+            const float al = (float)(a.blend_n - (tg + 1)) / (float)a.blend_n, be = 1.0f - al;
+            const float* pp = a.blend_prev + (((size_t)n * a.blend_Tp + (a.blend_Tp - a.blend_n + tg)) * plane_out +
+                                              (size_t)oh * a.Wo + ow) * 3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (c0 + r < 3) v4[r] = al * pp[c0 + r] + be * v4[r];
+          }
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             if (c0 + r < 3) op[c0 + r] = v4[r];

@@ -156,6 +156,12 @@ struct Win {
   int Tb, g0, first, count;
 };
 
+// GoP-boundary blending fused into C_out's epilogue (tok_decode_blend).
+struct Blend {
+  const float* prev;
+  int Tp, n;
+};
+
 const char* kKernelNames[K_IDS] = {
     "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
     "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
@@ -166,9 +172,15 @@ const char* kKernelNames[K_IDS] = {
 // through their global numbers) and writes the window `ow` of the output.
 tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_kind, int N, const Win& iw, int Hi,
                 int Wi, int Cin, void* out, int out_kind, const Win& ow, int Ho, int Wo, const void* resid,
-                float4* stats, hipStream_t s, const uint8_t* in_scale = nullptr, uint8_t* out_scale = nullptr) {
+                float4* stats, hipStream_t s, const uint8_t* in_scale = nullptr, uint8_t* out_scale = nullptr,
+                const Blend* blend = nullptr) {
   ConvLaunch a;
   std::memset(&a, 0, sizeof(a));
+  if (blend) {
+    a.blend_prev = blend->prev;
+    a.blend_Tp = blend->Tp;
+    a.blend_n = blend->n;
+  }
   const int CH = m->prec == P_BF16 ? 32 : (m->prec == P_FP8 ? 64 : 16);  // input chunking
   const int CHo = out_kind == OUT_FP8 ? 64 : (m->prec == P_F32 ? 16 : 32);
   a.in = in;
@@ -434,7 +446,8 @@ Fp8Plan make_fp8_plan(const Dims& d) {
 }
 
 tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xhat, void* ws, size_t ws_bytes,
-                      hipStream_t s) {
+                      hipStream_t s,
+                      const Blend* blend) {
   const Fp8Plan p = make_fp8_plan(d);
   if (p.total > ws_bytes)
     return fail(TOK_EWORKSPACE, "fp8 decode workspace needs " + std::to_string(p.total) + " bytes");
@@ -479,7 +492,7 @@ tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xh
                    s, u8(p.Ssc), u8(p.Csc)));
   }
   return conv(m, L_CONV_OUT, CM_S1, at(p.C), IN_ACT, N, w0, H, W, 64, xhat, OUT_RGB32, w0, H, W, nullptr, nullptr, s,
-              u8(p.Csc));
+              u8(p.Csc), nullptr, blend);
 }
 
 }  // namespace
@@ -739,13 +752,17 @@ tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, in
   return TOK_OK;
 }
 
-tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, int W2, float* xhat, void* ws,
-                      size_t ws_bytes, hipStream_t s) {
+namespace {
+
+tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, int W2, float* xhat, void* ws,
+                       size_t ws_bytes, hipStream_t s, const Blend* blend) {
   if (!m || !codes || !xhat || !ws) return fail(TOK_EINVAL, "null argument");
   if (T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
   Dims d;
   if (!make_dims(N, 4 * (T2 - 1) + 1, 4 * H2, 4 * W2, &d)) return fail(TOK_ESHAPE, "bad latent shape");
-  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s);
+  if (blend && (!blend->prev || blend->n < 1 || blend->n > d.T || blend->n > blend->Tp))
+    return fail(TOK_EINVAL, "blend needs prev and 1 <= n <= T, T_prev");
+  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend);
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))
     return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
@@ -770,7 +787,7 @@ tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, i
     TOK_TRY(resblocks(m, L_D_RB1_A, N_D_RB1_A, w, d, c.l0, false, chunked, L0, s));
     const Win ow{d.T, 0, c.l0.g0 + c.l0.first, c.l0.count};
     TOK_TRY(conv(m, L_CONV_OUT, CM_S1, w.l0a(), IN_ACT, N, c.l0, d.H, d.W, 64, xhat, OUT_RGB32, ow, d.H, d.W, nullptr,
-                 nullptr, s));
+                 nullptr, s, nullptr, nullptr, blend));
     if (L1 < d.T2) {
       TOK_TRY(shift_cache(w.l2(), c.l2, N, f2b, kCache2, s));
       TOK_TRY(shift_cache(w.l1(), c.l1, N, f1b, kCache1, s));
@@ -778,6 +795,19 @@ tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, i
     }
   }
   return TOK_OK;
+}
+
+}  // namespace
+
+tok_status tok_decode(tok_model* m, const float* codes, int N, int T2, int H2, int W2, float* xhat, void* ws,
+                      size_t ws_bytes, hipStream_t s) {
+  return decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, nullptr);
+}
+
+tok_status tok_decode_blend(tok_model* m, const float* codes, int N, int T2, int H2, int W2, const float* prev,
+                            int T_prev, int n, float* xhat, void* ws, size_t ws_bytes, hipStream_t s) {
+  const Blend b{prev, T_prev, n};
+  return decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, &b);
 }
 
 }  // extern "C"

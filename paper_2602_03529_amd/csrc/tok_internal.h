@@ -100,6 +100,11 @@ struct ConvLaunch {
   const uint8_t* in_scale;
   uint8_t* out_scale;
   const float* wscale;
+  // OUT_RGB32 only: GoP-boundary blending (Sec. 4.2, Eq. 2) of global output
+  // frames t < blend_n with frame blend_Tp - blend_n + t of blend_prev
+  // (float NDHWC, blend_Tp frames per clip); null for none.
+  const float* blend_prev;
+  int blend_Tp, blend_n;
 };
 
 // Tile geometry per mode (output rows x cols per workgroup).

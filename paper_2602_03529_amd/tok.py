@@ -113,16 +113,26 @@ class TokModel:
             C.byref(d) if d is not None else None, _ptr(kp), _ptr(ws), ws.numel(), _stream(dev)))
         return dict(z=zt, codes=codes, idx=idx, keep=kp)
 
-    def decode(self, codes: torch.Tensor, out=None, ws=None):
-        """codes: float32 (N,T2,H2,W2,6) -> x_hat float32 (N,4(T2-1)+1,4H2,4W2,3)."""
+    def decode(self, codes: torch.Tensor, out=None, ws=None, prev: torch.Tensor | None = None, blend_n: int = 2):
+        """codes: float32 (N,T2,H2,W2,6) -> x_hat float32 (N,4(T2-1)+1,4H2,4W2,3).
+        With prev (N,T_prev,4H2,4W2,3), the previous GoP's reconstruction, the
+        first blend_n frames are blended with its last ones (Sec. 4.2, Eq. 2)
+        inside the decoder's last conv."""
         N, T2, H2, W2, _ = codes.shape
         _need(codes, torch.float32, (N, T2, H2, W2, 6), "codes")
         T, H, W = 4 * (T2 - 1) + 1, 4 * H2, 4 * W2
         xh = out if out is not None else torch.empty((N, T, H, W, 3), dtype=torch.float32, device=codes.device)
         if ws is None:
             ws = self.workspace(N, T, H, W, L.TOK_WS_DECODE if self.precision == "fp8" else L.TOK_WS_ROUNDTRIP)
-        L.check("tok_decode", self.lib.tok_decode(self.handle, _ptr(codes), N, T2, H2, W2, _ptr(xh), _ptr(ws),
-                                                  ws.numel(), _stream(codes.device)))
+        if prev is None:
+            L.check("tok_decode", self.lib.tok_decode(self.handle, _ptr(codes), N, T2, H2, W2, _ptr(xh), _ptr(ws),
+                                                      ws.numel(), _stream(codes.device)))
+        else:
+            Tp = prev.shape[1]
+            _need(prev, torch.float32, (N, Tp, H, W, 3), "prev")
+            L.check("tok_decode_blend", self.lib.tok_decode_blend(
+                self.handle, _ptr(codes), N, T2, H2, W2, _ptr(prev), Tp, int(blend_n), _ptr(xh), _ptr(ws), ws.numel(),
+                _stream(codes.device)))
         return xh
 
 
@@ -374,6 +384,25 @@ def gop_blend(prev: torch.Tensor, xhat: torch.Tensor, n: int = 2):
     L.check("tok_gop_blend", L.lib().tok_gop_blend(_ptr(prev), Tp, _ptr(xhat), N, T, H, W, int(n),
                                                    _stream(xhat.device)))
     return xhat
+
+
+class GopStream:
+    """Decodes consecutive GoPs of a stream with boundary blending (Sec. 4.2,
+    Eq. 2): each GoP's first n frames are blended, inside the decoder, with
+    the last n frames of the previous GoP's output, which the stream keeps."""
+
+    def __init__(self, model: TokModel, n: int = 2):
+        self.model, self.n, self.tail = model, int(n), None
+
+    def decode(self, codes: torch.Tensor, ws=None) -> torch.Tensor:
+        if self.tail is not None and self.tail.shape[0] != codes.shape[0]:
+            raise ValueError("batch size changed within a stream")
+        xh = self.model.decode(codes, ws=ws, prev=self.tail, blend_n=self.n)
+        self.tail = xh[:, xh.shape[1] - self.n:].contiguous()
+        return xh
+
+    def reset(self):
+        self.tail = None
 
 
 class TokServer:

@@ -241,3 +241,78 @@ def test_coding_errors(tk):
     with pytest.raises(TokError):
         tk.residual_compress(torch.zeros((1, 3, 6, 8, 3), dtype=torch.uint8, device="cuda"),
                              torch.zeros((1, 3, 6, 8, 3), device="cuda"), 0.1)
+
+
+# ---- blending fused into the decoder's last conv (tok_decode_blend) ------------------
+
+def uniform_codes(seed, N, T2, H2, W2):
+    rng = np.random.default_rng(seed)
+    levels = np.array([8, 8, 8, 5, 5, 5])
+    q = np.floor(rng.uniform(size=(N, T2, H2, W2, 6)) * levels).astype(np.int64) - levels // 2
+    return np.ascontiguousarray(q / (levels // 2), np.float32)
+
+
+@pytest.fixture(scope="module")
+def f32_model(tk):
+    import synth
+    from tests import gpu_common as G
+    return tk.TokModel(synth.flatten_weights(G.weights(True)), "f32")
+
+
+def test_fused_blend_matches_oracle_decode_then_blend(tk, f32_model):
+    """FP32 decode of seeded codes with the previous GoP's frames blended in
+    C_out's epilogue, against the oracle's decode followed by its blend:
+    within the FP32 reconstruction tolerance."""
+    from tests import gpu_common as G
+    codes = uniform_codes(40, 1, 3, 16, 16)
+    rng = np.random.default_rng(41)
+    prev = rng.normal(0, 1, (1, 9, 64, 64, 3)).astype(np.float32)
+    ref = K.gop_blend(prev, O.decode(codes.astype(np.float64), G.weights64(True)), 2)
+    got = f32_model.decode(torch.from_numpy(codes).cuda(), prev=torch.from_numpy(prev).cuda(), blend_n=2)
+    got = got.cpu().numpy()
+    err = float(np.abs(got - ref).max())
+    print("fused blend vs oracle: max-abs %.3g" % err, flush=True)
+    assert err <= G.F32_RECON_TOL
+
+
+@pytest.mark.parametrize("prec,n", [("f32", 2), ("f32", 3), ("bf16", 2), ("fp8", 2)])
+def test_fused_blend_equals_decode_then_blend_kernel(tk, prec, n):
+    import synth
+    from tests import gpu_common as G
+    m = tk.TokModel(synth.flatten_weights(G.weights(True)), prec)
+    codes = torch.from_numpy(uniform_codes(42, 2, 3, 12, 20)).cuda()
+    prev = torch.from_numpy(np.random.default_rng(43).normal(0, 1, (2, 5, 48, 80, 3)).astype(np.float32)).cuda()
+    plain = m.decode(codes)
+    fused = m.decode(codes, prev=prev, blend_n=n)
+    sep = tk.gop_blend(prev, plain.clone(), n)
+    torch.cuda.synchronize()
+    assert torch.equal(fused[:, n:], plain[:, n:])
+    p, f, s = prev[:, -n:].double().abs(), fused[:, :n].double(), sep[:, :n].double()
+    assert bool(((f - s).abs() <= 4 * U * (p + plain[:, :n].double().abs())).all())
+
+
+def test_gop_stream_and_chunked_decode(tk, f32_model):
+    codes = [torch.from_numpy(uniform_codes(50 + k, 1, 3, 8, 12)).cuda() for k in range(3)]
+    st = tk.GopStream(f32_model, n=2)
+    outs = [st.decode(c).clone() for c in codes]
+    ws = torch.empty(f32_model.workspace_size(1, 9, 32, 48, stream=True), dtype=torch.uint8, device="cuda")
+    for k in range(3):
+        plain = f32_model.decode(codes[k])
+        if k == 0:
+            assert torch.equal(outs[0], plain)
+            continue
+        prev = outs[k - 1][:, -2:].contiguous()
+        whole = f32_model.decode(codes[k], prev=prev, blend_n=2)
+        chunked = f32_model.decode(codes[k], prev=prev, blend_n=2, ws=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[k], whole) and torch.equal(chunked, whole)
+        assert torch.equal(whole[:, 2:], plain[:, 2:]) and not torch.equal(whole[:, :1], plain[:, :1])
+
+
+def test_fused_blend_errors(tk, f32_model):
+    from paper_2602_03529_amd._lib import TokError
+    codes = torch.from_numpy(uniform_codes(60, 1, 2, 4, 4)).cuda()
+    with pytest.raises(TokError):
+        f32_model.decode(codes, prev=torch.zeros((1, 1, 16, 16, 3), device="cuda"), blend_n=2)
+    with pytest.raises(TokError):
+        f32_model.decode(codes, prev=torch.zeros((1, 9, 16, 16, 3), device="cuda"), blend_n=6)
