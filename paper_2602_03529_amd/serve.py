@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 
 
 def run(clips=256, rate=40.0, T=17, budget_gb=8.0, slots=4, max_batch=4, precision="bf16", seed=3,
-        pixel_seeds=2, resolutions=None, max_drop=0.5, log=None):
+        pixel_seeds=2, resolutions=None, max_drop=0.5, drop_mode=1, log=None):
     import torch
 
     import synth
@@ -69,7 +69,7 @@ def run(clips=256, rate=40.0, T=17, budget_gb=8.0, slots=4, max_batch=4, precisi
             if delay > 0:
                 time.sleep(delay)
             px = pool[(r.H, r.W)][r.pixel_seed % pixel_seeds]
-            d = tok.Drop(mode=1, rate=r.drop_rate, seed=seed, clip_id0=r.clip_id)
+            d = tok.Drop(mode=drop_mode, rate=r.drop_rate, seed=seed, clip_id0=r.clip_id)
             tickets[i] = sv.submit(px, d)
         submitted.set()
 
@@ -98,7 +98,7 @@ def run(clips=256, rate=40.0, T=17, budget_gb=8.0, slots=4, max_batch=4, precisi
     batches = np.bincount([r["batch_size"] for r in results])
     return dict(
         clips=len(reqs), frames=frames, rate_per_s=rate, budget_gb=budget_gb, slots=slots, max_batch=max_batch,
-        precision=precision, failed=int(sum(r["status"] != 0 for r in results)),
+        precision=precision, drop_mode=drop_mode, failed=int(sum(r["status"] != 0 for r in results)),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
         mean_queue_ms=float(qms.mean()), makespan_s=makespan, frames_per_s=frames / makespan,
         arrival_span_s=reqs[-1].arrival_s, peak_arena_gb=st["bytes_peak"] / (1 << 30),
@@ -116,9 +116,13 @@ def main():
     ap.add_argument("--max-batch", type=int, default=4)
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--pixel-seeds", type=int, default=2)
+    ap.add_argument("--drop", choices=["bernoulli", "rows", "similarity"], default="bernoulli",
+                    help="per-clip token drop: seeded Bernoulli tokens, lost rows, or similarity-based selection")
     args = ap.parse_args()
+    mode = {"bernoulli": 1, "rows": 2, "similarity": 4}[args.drop]
     out = run(args.clips, args.rate, args.frames, args.budget_gb, args.slots, args.max_batch, args.precision,
-              pixel_seeds=args.pixel_seeds, log=lambda m: print("serve: " + m, file=sys.stderr, flush=True))
+              pixel_seeds=args.pixel_seeds, drop_mode=mode,
+              log=lambda m: print("serve: " + m, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 
 

@@ -43,12 +43,16 @@ def _alone(tk, model, px, drop):
     return {k: v[0].cpu().numpy() for k, v in out.items() if k != "z"}, xh[0].cpu().numpy()
 
 
-def test_mixed_stream_equals_alone(tk, model):
+@pytest.mark.parametrize("modes", [(1,), (1, 2, 4)])
+def test_mixed_stream_equals_alone(tk, model, modes):
+    """Bernoulli drops only, and a mix of Bernoulli, lost-row and
+    similarity-based (Sec. 4.3, Eq. 3) drops across the clips of the stream."""
     rng = np.random.default_rng(7)
     reqs = []
     for i in range(14):
         T, H, W = SHAPES[int(rng.integers(len(SHAPES)))]
-        d = tk.Drop(mode=1, rate=float(rng.uniform(0, 0.5)), seed=11, clip_id0=1000 + i)
+        mode = modes[i % len(modes)]
+        d = tk.Drop(mode=mode, rate=float(rng.uniform(0, 0.5)), seed=11, clip_id0=1000 + i)
         reqs.append((i, T, H, W, _clip(i, T, H, W), d))
     budget = 3 * max(model.workspace_size(1, T, H, W) for _, T, H, W, _, _ in reqs) + (64 << 20)
     sv = tk.TokServer(model, budget, slots=3, max_batch=3)
