@@ -62,10 +62,10 @@ template <> struct Geo<CM_UP> {
   static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
 template <> struct Geo<CM_S1T> : Geo<CM_S1> {};
-// im2col first layer: the "halo" is the tile itself (one row per output
-// position), one tap, one stage per 96-wide K chunk.
+// im2col first layer: no halo staging (the MFMA operands are gathered from
+// the normalised pixel tile), one tap, one stage per 32-wide (bf16) K chunk.
 template <> struct Geo<CM_I2C> {
-  static constexpr int WR = 2, TW = 64, TH = 8, HH = TH, HW = TW;
+  static constexpr int WR = 2, TW = 64, TH = 8, HH = 1, HW = 1;
   static constexpr int MB = 8, WT = 1, KTS = 1;
 };
 
@@ -84,6 +84,12 @@ template <> struct Geo<CM_UPF> {
 #define TOK_S1_TALL 1
 #endif
 constexpr bool kS1Tall = TOK_S1_TALL != 0;
+
+// Workgroups per CU the bf16 first-layer kernel is compiled for.
+#ifndef TOK_I2C_OCC
+#define TOK_I2C_OCC 3
+#endif
+constexpr int kI2cOcc = TOK_I2C_OCC;
 
 // Output-tile-local position of lane l16 in position block m of a wave.
 template <int MODE>
@@ -183,7 +189,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS, bool DB>
-__global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch a) {
+__global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC == P_BF16) ? kI2cOcc : 2))
+    conv3d_kernel(ConvLaunch a) {
   using G = Geo<MODE>;
   using O = Op<PREC>;
   constexpr bool F8 = PREC == P_FP8;
@@ -207,7 +214,9 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   __shared__ uint4 lds_a[NBUF][HQ];
   __shared__ uint4 lds_w[NBUF][WQ];
   __shared__ uint16_t lds_sc[SCN];
-  __shared__ float lds_px[PXN];
+  __shared__ __align__(16) float lds_px[PXN];
+  constexpr int WQI = MODE == CM_I2C ? NT * 4 * (kI2cK / O::CH) : 1;  // im2col: every stage's weights
+  __shared__ uint4 lds_wi[WQI];
   __shared__ float red[kWaves][32];
   __shared__ float gmean[32];
 
@@ -329,52 +338,35 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
   // QE consecutive K entries k = (kt*9 + kh*3 + kw)*3 + c of one position.
   constexpr int PXW = G::TW + 2, PXH = G::TH + 2;
   auto stage_px = [&]() {
-    for (int e = tid; e < 3 * PXH * PXW; e += kThreads) {
-      const int f = e / (PXH * PXW), r = (e / PXW) % PXH, c = e % PXW;
+    // The 3 x PXH row segments of PXW pixels (3 bytes each) as bytes: thread
+    // t handles bytes t, t + 256, ...; every load is issued before the first
+    // is used, so the tile waits for one memory latency, not one per pixel.
+    constexpr int SEG = PXW * 3, NBYTES = 3 * PXH * SEG, NB8 = (NBYTES + kThreads - 1) / kThreads;
+    uint32_t vb[NB8];
+#pragma unroll
+    for (int k = 0; k < NB8; ++k) {
+      const int b = tid + k * kThreads;
+      const int seg = b / SEG, o = b - seg * SEG;
+      const int f = seg / PXH, r = seg - f * PXH;
+      const int c = o / 3, ch = o - 3 * c;
       const int hs = h0 - 1 + r, ws = w0 - 1 + c;
       const int g = max(a.go0 + to + f - 2, 0) - a.gi0;  // causal clamp of the input frame
-      float px[3] = {0.f, 0.f, 0.f};
-      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
-        const uint8_t* pp = reinterpret_cast<const uint8_t*>(a.in) + (((size_t)n * a.Ti + g) * a.Hi * a.Wi +
-                                                                          (size_t)hs * a.Wi + ws) * 3;
+      vb[k] = 0x100u;  // outside the frame (or past the last byte): zero
+      if (b < NBYTES && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi)
+        vb[k] = reinterpret_cast<const uint8_t*>(a.in)[(((size_t)n * a.Ti + g) * a.Hi * a.Wi + (size_t)hs * a.Wi +
+                                                        ws) * 3 + ch];
+    }
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) px[ch] = (float)pp[ch] / 127.5f - 1.0f;
+    for (int k = 0; k < NB8; ++k) {
+      const int b = tid + k * kThreads;
+      if (b < NBYTES) {
+        const int seg = b / SEG, o = b - seg * SEG;
+        const int c = o / 3, ch = o - 3 * c;
+        lds_px[(seg * PXW + c) * 4 + ch] = vb[k] == 0x100u ? 0.f : (float)vb[k] / 127.5f - 1.0f;
       }
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) lds_px[e * 4 + ch] = px[ch];
-      lds_px[e * 4 + 3] = 0.f;
     }
+    for (int p = tid; p < 3 * PXH * PXW; p += kThreads) lds_px[p * 4 + 3] = 0.f;  // the 4th (zero) channel
   };
-  auto stage_i2c = [&](int st) {
-    const uint4* wsrc = wbase + (size_t)st * WQ;
-#pragma unroll
-    for (int base = wave * 64; base < WQ; base += kThreads) lds_dma16(wsrc + base + lane, &lds_w[0][base]);
-    constexpr int QE = O::QE;
-    const int q = tid & 3;
-    int off[QE];
-#pragma unroll
-    for (int x = 0; x < QE; ++x) {
-      const int k = st * O::CH + q * QE + x;
-      const int tap = k / 3, ch = k % 3;
-      const int kt = tap / 9, kh = (tap / 3) % 3, kw = tap % 3;
-      off[x] = k < 81 ? ((kt * PXH + kh) * PXW + kw) * 4 + ch : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < (G::TH * G::TW) / 64; ++u) {
-      const int row = (tid >> 2) + 64 * u;
-      const int base = ((row / G::TW) * PXW + (row % G::TW)) * 4;
-      float v[QE];
-#pragma unroll
-      for (int x = 0; x < QE; ++x) v[x] = off[x] >= 0 ? lds_px[base + off[x]] : 0.f;
-      uint4 val;
-      if constexpr (PREC == P_BF16)
-        val = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
-      else
-        val = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3]));
-      lds_a[0][row * 4 + (q ^ swz(row))] = val;
-    }
-  };
-
   // The 9 spatial taps of one stage: every wave multiplies its MB position
   // blocks by the NB output-channel blocks.
   auto compute = [&](int buf) {
@@ -425,24 +417,6 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
             for (int b = 0; b < NB; ++b) mfma_fp8(acc[m][b], wq[b], aq, sb);
           }
         }
-      }
-      return;
-    }
-    if constexpr (MODE == CM_I2C) {
-      uint4 wq[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int row = b * 16 + l16;
-        wq[b] = lds_w[buf][row * 4 + (g4 ^ swz(row))];
-      }
-#pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        int i, j;
-        out_local<MODE>(wave, m, l16, &i, &j);
-        const int row = i * G::TW + j;
-        const uint4 aq = lds_a[buf][row * 4 + (g4 ^ swz(row))];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
       }
       return;
     }
@@ -523,7 +497,58 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
     }
   };
 
-  if constexpr (DB) {
+  // im2col first layer: K chunk st of a position is taps (st CH + 4 v) / 4 ..,
+  // 4 channels each (the 4th zero); a lane's operand quad is read straight
+  // from the normalised pixel tile (one 16-byte read per tap) and converted.
+  auto compute_i2c = [&](int st) {
+    constexpr int QE = O::QE, TPQ = QE / 4;
+    uint4 wq[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int row = b * 16 + l16;
+      wq[b] = lds_wi[st * WQ + row * 4 + (g4 ^ swz(row))];
+    }
+    int off[TPQ];
+#pragma unroll
+    for (int x = 0; x < TPQ; ++x) {
+      const int tap = (st * O::CH + g4 * QE) / 4 + x;
+      const int kt = tap / 9, kh = (tap / 3) % 3, kw = tap % 3;
+      off[x] = tap < 27 ? ((kt * PXH + kh) * PXW + kw) * 4 : -1;
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      int i, j;
+      out_local<MODE>(wave, m, l16, &i, &j);
+      const int base = (i * PXW + j) * 4;
+      float v[QE];
+#pragma unroll
+      for (int x = 0; x < TPQ; ++x) {
+        const float4 t4 = off[x] >= 0 ? *reinterpret_cast<const float4*>(&lds_px[base + off[x]])
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[4 * x] = t4.x;
+        v[4 * x + 1] = t4.y;
+        v[4 * x + 2] = t4.z;
+        v[4 * x + 3] = t4.w;
+      }
+      uint4 aq;
+      if constexpr (PREC == P_BF16)
+        aq = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+      else
+        aq = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3]));
+#pragma unroll
+      for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
+    }
+  };
+
+  if constexpr (MODE == CM_I2C) {
+    // pixels and all the weights once, then every K chunk without further staging
+    stage_px();
+#pragma unroll
+    for (int base = wave * 64; base < WQI; base += kThreads) lds_dma16(wbase + base + lane, &lds_wi[base]);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int st = 0; st < nstages; ++st) compute_i2c(st);
+  } else if constexpr (DB) {
     issue_async(0, 0);
     for (int st = 0; st < nstages; ++st) {
       // stage st has landed in buffer st & 1, and every wave is done with
@@ -534,16 +559,12 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : 2) conv3d_kernel(ConvLaunch
       compute(st & 1);
     }
   } else {
-    if constexpr (MODE == CM_I2C) {
-      stage_px();
-    }
     for (int st = 0; st < nstages; ++st) {
       if constexpr (MODE == CM_S1T) {
         if (src_frame(st / a.in_chunks) >= a.Ti) continue;  // beyond the last gradient frame (uniform per block)
       }
       __syncthreads();
-      if constexpr (MODE == CM_I2C) stage_i2c(st);
-      else issue_async(st, 0);
+      issue_async(st, 0);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // direct-to-LDS loads have landed
       __syncthreads();
       compute(0);
@@ -1334,14 +1355,14 @@ __device__ float pack_value(const float* __restrict__ w, const PackGeom& g, size
     return v;
   }
   if (g.mode == CM_I2C) {
-    // [ct][chunk][o][quad][QE]: K index k = (kt*9 + kh*3 + kw)*3 + c, zero past 81
+    // [ct][chunk][o][quad][QE]: K index k = (kt*9 + kh*3 + kw)*4 + c, zero for c = 3 and past 108
     const int ck = (int)(e % g.chunks); e /= g.chunks;
     const int ct = (int)e;
     const int q = pq ^ swz(o);
     const int co = ct * g.nt + o, k = ck * g.CH + q * g.QE + x;
-    if (co >= g.Cout || k >= 81) return 0.f;
-    const int tp = k / 3;
-    return W(co, k % 3, tp / 9, (tp / 3) % 3, tp % 3);
+    if (co >= g.Cout || k >= 108 || (k & 3) == 3) return 0.f;
+    const int tp = k >> 2;
+    return W(co, k & 3, tp / 9, (tp / 3) % 3, tp % 3);
   }
   const int tap = (int)(e % 9); e /= 9;
   const int ck = (int)(e % g.chunks); e /= g.chunks;
@@ -1429,7 +1450,7 @@ PackGeom pack_geom(int Cout, int Cin, int prec, int mode, size_t* elems) {
   g.co = co;
   g.nt = co >= 64 ? 64 : 16;
   g.chunks = (ci + g.CH - 1) / g.CH;
-  if (mode == CM_I2C) g.chunks = kI2cK / g.CH;  // K = 27 taps x 3 channels, padded
+  if (mode == CM_I2C) g.chunks = kI2cK / g.CH;  // K = 27 taps x 4 channels, padded
   if (mode == CM_UPF) g.R = 2 * 2 * g.chunks * 16;
   else if (mode == CM_S1T) g.R = 2 * 3 * g.chunks * 9;
   else if (mode == CM_I2C) g.R = g.chunks;

@@ -23,11 +23,12 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 // in time, spatially flipped, channels transposed; output frame 0 uses the
 // temporal taps folded by the causal clamp (frame 0 is read three times).
 // CM_I2C: the first layer (3 input channels, uint8 pixels): each output
-// position's 27 taps x 3 channels are gathered in LDS into one K = 81 (padded
-// to 96) vector, so the layer runs as a single-tap product with ~9x fewer
-// MFMAs than 27 taps of a 3-channel (padded) chunk.
+// position's 27 taps x 3 channels are gathered in LDS into one K vector of 27
+// taps x 4 (the 4th channel zero, so a tap is one 16-byte LDS read) padded to
+// 128, and the layer runs as a single-tap product with ~7x fewer MFMAs than
+// 27 taps of a 3-channel (padded) chunk.
 enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3, CM_S1T = 4, CM_I2C = 5 };
-constexpr int kI2cK = 96;  // 27 taps x 3 channels, padded to whole 32-element bf16 chunks
+constexpr int kI2cK = 128;  // 27 taps x 4 channels, padded to whole 32-element bf16 chunks
 enum InKind { IN_ACT = 0, IN_U8 = 1 };
 // OUT_ACT: chunked activations of the kernel's output precision (bf16 for
 // P_FP8 kernels); OUT_FP8: MX-FP8 activations; OUT_RGB32: float NDHWC (3 ch).
