@@ -161,7 +161,8 @@ tok_status tok_drop(const tok_drop_desc* drop, float* codes, uint8_t* keep, int 
  * comparison is of rationals, not of rounded cosines).
  * codes: device float32 (N,T2,H2,W2,6), dropped tokens zero-filled in place.
  * keep: device uint8 (N,T2,H2,W2) output or NULL.  ws: device scratch of at
- * least tok_select_workspace_size bytes; its contents are not preserved.
+ * least tok_select_workspace_size bytes, 16-byte aligned; its contents are
+ * not preserved.  codes must be 8-byte aligned.
  * Errors: TOK_EINVAL (null codes / ws), TOK_ESHAPE (N > 65535 or a clip of
  * 2^31 tokens or more), TOK_EWORKSPACE. */
 tok_status tok_select_workspace_size(int N, int T2, int H2, int W2, size_t* bytes);
@@ -185,7 +186,7 @@ tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, in
 /* Upper bound of the stream length: every token valid. */
 tok_status tok_packets_max_bytes(int N, int T2, int H2, int W2, size_t* bytes);
 
-/* Sender.  idx: device int32 (N,T2,H2,W2) FSQ indices (tok_encode's idx).
+/* Sender.  idx: device int32 (N,T2,H2,W2) FSQ indices (tok_encode's idx), 4-byte aligned.
  * keep: device uint8 (N,T2,H2,W2) mask, or NULL for all valid.  out: device
  * buffer, 4-byte aligned, of out_bytes >= tok_packets_max_bytes bytes.
  * offsets: device uint64 [N T2 H2 + 1], receives each packet's byte offset in
@@ -218,8 +219,8 @@ tok_status tok_reassemble(const uint8_t* buf, size_t bytes, const uint64_t* offs
  * entries (entries past it are not written), clip_offsets uint64 [N + 1]:
  * clip n's entries are [clip_offsets[n], clip_offsets[n+1]) (the total may
  * exceed capacity; N H W 3 entries always fit).  ws: device scratch of
- * tok_residual_workspace_size bytes.  Needs H, W multiples of 4 and
- * N H W 3 < 2^32. */
+ * tok_residual_workspace_size bytes.  index, value and ws 4-byte aligned,
+ * clip_offsets 8-byte aligned.  Needs H, W multiples of 4 and N H W 3 < 2^32. */
 tok_status tok_residual_workspace_size(int N, int H, int W, size_t* bytes);
 tok_status tok_residual_compress(const uint8_t* x, const float* xhat, int N, int T, int H, int W,
                                  float theta, float* r, uint32_t* index, float* value,

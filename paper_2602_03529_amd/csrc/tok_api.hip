@@ -675,6 +675,8 @@ tok_status tok_encode(tok_model* m, const uint8_t* x, int N, int T, int H, int W
     if (!codes) return fail(TOK_EINVAL, "similarity-based selection needs the codes output");
     if (ws_bytes < similarity_ws_bytes(N, d.T2, d.H2, d.W2))
       return fail(TOK_EWORKSPACE, "workspace too small for the similarity selection");
+    if ((reinterpret_cast<uintptr_t>(codes) & 7) || (reinterpret_cast<uintptr_t>(ws) & 15))
+      return fail(TOK_EINVAL, "similarity selection needs 8-byte aligned codes and a 16-byte aligned workspace");
     if ((long long)d.T2 * d.H2 * d.W2 > 0x7fffffffLL || N > 65535)
       return fail(TOK_ESHAPE, "similarity selection needs N <= 65535 and under 2^31 tokens per clip");
   }
@@ -746,7 +748,8 @@ tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, in
   if (N > 65535 || (long long)T2 * H2 * W2 > 0x7fffffffLL)
     return fail(TOK_ESHAPE, "need N <= 65535 and under 2^31 tokens per clip");
   if (ws_bytes < similarity_ws_bytes(N, T2, H2, W2)) return fail(TOK_EWORKSPACE, "workspace too small");
-  if (reinterpret_cast<uintptr_t>(codes) & 7) return fail(TOK_EINVAL, "codes must be 8-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(codes) & 7) || (reinterpret_cast<uintptr_t>(ws) & 15))
+    return fail(TOK_EINVAL, "codes must be 8-byte and ws 16-byte aligned");
   TOK_HIP(launch_similarity_drop(codes, keep, N, T2, H2, W2,
                                  similarity_drop_count(rate, (long long)(T2 - 1) * H2 * W2), ws, s));
   return TOK_OK;
@@ -760,8 +763,9 @@ tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, 
   if (T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
   Dims d;
   if (!make_dims(N, 4 * (T2 - 1) + 1, 4 * H2, 4 * W2, &d)) return fail(TOK_ESHAPE, "bad latent shape");
-  if (blend && (!blend->prev || blend->n < 1 || blend->n > d.T || blend->n > blend->Tp))
-    return fail(TOK_EINVAL, "blend needs prev and 1 <= n <= T, T_prev");
+  if (blend && (!blend->prev || blend->n < 1 || blend->n > d.T || blend->n > blend->Tp ||
+                (reinterpret_cast<uintptr_t>(blend->prev) & 3)))
+    return fail(TOK_EINVAL, "blend needs a 4-byte aligned prev and 1 <= n <= T, T_prev");
   if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend);
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))

@@ -34,7 +34,8 @@ tok_status tok_packetize(const int32_t* idx, const uint8_t* keep, int N, int T2,
   if (!idx || !out || !offsets) return fail(TOK_EINVAL, "null argument");
   if (!latent_ok(N, T2, H2, W2) || (long long)N * T2 * H2 > 0xffffffffLL)
     return fail(TOK_ESHAPE, "bad latent shape (at most 2^32 - 1 rows)");
-  if (!aligned(out, 4) || !aligned(offsets, 8)) return fail(TOK_EINVAL, "out must be 4-byte, offsets 8-byte aligned");
+  if (!aligned(out, 4) || !aligned(offsets, 8) || !aligned(idx, 4))
+    return fail(TOK_EINVAL, "idx and out must be 4-byte, offsets 8-byte aligned");
   if (out_bytes < (size_t)packets_max_bytes(N, T2, H2, W2))
     return fail(TOK_EWORKSPACE, "out smaller than tok_packets_max_bytes");
   TOK_HIP(launch_packetize(idx, keep, N, T2, H2, W2, out, reinterpret_cast<unsigned long long*>(offsets), s));
@@ -64,8 +65,9 @@ tok_status tok_residual_compress(const uint8_t* x, const float* xhat, int N, int
   if (!x || !xhat || !r || !clip_offsets || !ws || (capacity && (!index || !value)))
     return fail(TOK_EINVAL, "null argument");
   if (!pixels_ok(N, T, H, W)) return fail(TOK_ESHAPE, "need H, W multiples of 4 and N H W 3 < 2^32");
-  if (!aligned(x, 16) || !aligned(xhat, 16) || !aligned(r, 16) || !aligned(clip_offsets, 8))
-    return fail(TOK_EINVAL, "x, xhat and r must be 16-byte aligned");
+  if (!aligned(x, 16) || !aligned(xhat, 16) || !aligned(r, 16) || !aligned(clip_offsets, 8) || !aligned(ws, 4) ||
+      !aligned(index, 4) || !aligned(value, 4))
+    return fail(TOK_EINVAL, "x, xhat and r must be 16-byte, clip_offsets 8-byte, ws, index and value 4-byte aligned");
   if (ws_bytes < residual_ws_bytes(N, H, W)) return fail(TOK_EWORKSPACE, "workspace too small");
   TOK_HIP(launch_residual(x, xhat, N, T, H, W, theta, r, index, value, (long long)capacity,
                           reinterpret_cast<unsigned long long*>(clip_offsets), ws, s));
