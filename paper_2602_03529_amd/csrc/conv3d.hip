@@ -180,6 +180,18 @@ __device__ __forceinline__ void mfma_fp8(f32x4& acc, const i32x8& w, const i32x8
   acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, sb);
 }
 
+// The K = 64 (one tap x 64 channels) fp8 MFMA, 32 x 32 output (measured with
+// an in-bounds probe): lane l holds row / column l % 32 and 32 bytes of K; the
+// E8M0 scale of lane half h = l / 32 covers bytes 16 h .. 16 h + 15 of both
+// halves' lanes of that row / column; D register r of lane l is
+// D[8 (r / 4) + 4 h + r % 4][l % 32].  With ld_fp8_pair (lane half h takes
+// channel quads h and 2 + h) the scale of half h covers channels 32 h .. + 31,
+// i.e. exactly one MX block.
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+__device__ __forceinline__ void mfma_fp8_32(f32x16& acc, const i32x8& w, const i32x8& x, int sb) {
+  acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, sb);
+}
+
 // Map a linear block index to a virtual tile index so that the blocks one XCD
 // receives (hardware dispatches block b to XCD b % 8) are contiguous tiles.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -539,6 +551,206 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
       for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
     }
   };
+
+  // fp8 stride-1 64-channel convs: 32 x 32 x 64 MFMAs, one tap per
+  // instruction.  Wave tile 4 rows x 32 columns: position block m = output
+  // row i0 + m (32 positions), channel block c = 32 output channels.  Per kw
+  // the wave loads halo rows i0 .. i0 + 5 once and reuses them for kh = 0..2
+  // (output row m reads halo row m + kh).
+  constexpr bool F8W = F8 && MODE == CM_S1 && NB == 4;
+  if constexpr (F8W) {
+    f32x16 a32[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a32[m][c][r] = 0.f;
+    const int hh = lane >> 5, p32 = lane & 31;
+    const int i0 = 4 * (wave >> 1), j0 = 32 * (wave & 1) + p32;
+    for (int st = 0; st < nstages; ++st) {
+      __syncthreads();
+      issue_async(st, 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+#pragma unroll 1
+      for (int kw = 0; kw < 3; ++kw) {
+        i32x8 bq[6];
+        int sq[6];
+#pragma unroll
+        for (int hr = 0; hr < 6; ++hr) {
+          const int row = (i0 + hr) * G::HW + j0 + kw;
+          bq[hr] = ld_fp8_pair(lds_a[0], row, hh);
+          sq[hr] = (lds_sc[row] >> (8 * hh)) & 255;
+        }
+#pragma unroll
+        for (int kh = 0; kh < 3; ++kh) {
+          i32x8 wq[2];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) wq[c] = ld_fp8_pair(lds_w[0], (kh * 3 + kw) * NT + c * 32 + p32, hh);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) mfma_fp8_32(a32[m][c], wq[c], bq[m + kh], sq[m + kh]);
+        }
+      }
+    }
+    // ---- epilogue of the 32 x 32 layout: value r of (m, c) is channel
+    // ct NT + 32 c + 8 (r / 4) + 4 hh + r % 4 at position (i0 + m, j0)
+    const size_t plane_out = (size_t)a.Ho * a.Wo;
+    const int ow = w0 + j0;
+    if constexpr (OUT_KIND == OUT_FP8) {
+      const int res_chunks = a.Cout / OO::CH;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int oh = h0 + i0 + m;
+        const bool valid = (oh < a.Ho) && (ow < a.Wo);
+        const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
+        const size_t pos = (size_t)oh * a.Wo + ow;
+        float v[2][16];
+        float am[2] = {0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[c][4 * q + r] = a32[m][c][4 * q + r] * a.wscale[c0 + r] + a.bias[c0 + r];
+            if constexpr (RESID) {
+              if (valid) {
+                const uint2 rv = *reinterpret_cast<const uint2*>(
+                    reinterpret_cast<const char*>(a.resid) +
+                    ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
+                v[c][4 * q] += bf16_lo(rv.x); v[c][4 * q + 1] += bf16_hi(rv.x);
+                v[c][4 * q + 2] += bf16_lo(rv.y); v[c][4 * q + 3] += bf16_hi(rv.y);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) am[c] = fmaxf(am[c], fabsf(v[c][4 * q + r]));
+          }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) am[c] = fmaxf(am[c], __shfl_xor(am[c], 32));
+        const int e0 = fp8_block_exp(am[0]), e1 = fp8_block_exp(am[1]);
+        if (valid) {
+          char* orow = reinterpret_cast<char*>(a.out) + ((frame * a.out_chunks + ct) * plane_out + pos) * kChunkBytes;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const float f = ldexpf(1.0f, -(c == 0 ? e0 : e1));
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<uint32_t*>(orow + 32 * c + 8 * q + 4 * hh) =
+                  pack_fp8x4(v[c][4 * q] * f, v[c][4 * q + 1] * f, v[c][4 * q + 2] * f, v[c][4 * q + 3] * f);
+          }
+          if (hh == 0)
+            reinterpret_cast<uint16_t*>(a.out_scale)[(frame * a.out_chunks + ct) * plane_out + pos] =
+                (uint16_t)((e0 + 127) | ((e1 + 127) << 8));
+        }
+      }
+      return;
+    } else {
+      static_assert(OUT_KIND == OUT_ACT && OPREC == P_BF16, "fp8 convs store bf16 or fp8 activations");
+      // group g = channel / 2 of the 32 GroupNorm groups; this lane's items
+      // (c, q) hold groups 16 c + 4 q + 2 hh and + 1
+      float s_lo[8], s_hi[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s_lo[k] = s_hi[k] = 0.f;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int oh = h0 + i0 + m;
+        const bool valid = (oh < a.Ho) && (ow < a.Wo);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
+            float v4[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v4[r] = a32[m][c][4 * q + r] * a.wscale[c0 + r] + a.bias[c0 + r];
+            const int chunk = c0 / OO::CH, within = c0 % OO::CH;
+            const size_t off = (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
+                               ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * 2;
+            if (valid) {
+              if constexpr (RESID) {
+                const uint2 rv = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + off);
+                v4[0] += bf16_lo(rv.x); v4[1] += bf16_hi(rv.x);
+                v4[2] += bf16_lo(rv.y); v4[3] += bf16_hi(rv.y);
+              }
+              const uint2 pv = make_uint2(pack_bf16(v4[0], v4[1]), pack_bf16(v4[2], v4[3]));
+              *reinterpret_cast<uint2*>(reinterpret_cast<char*>(a.out) + off) = pv;
+              v4[0] = bf16_lo(pv.x); v4[1] = bf16_hi(pv.x); v4[2] = bf16_lo(pv.y); v4[3] = bf16_hi(pv.y);
+            }
+            if constexpr (STATS) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) a32[m][c][4 * q + r] = valid ? v4[r] : 0.f;  // keep final values
+              if (valid) {
+                s_lo[4 * c + q] += v4[0] + v4[1];
+                s_hi[4 * c + q] += v4[2] + v4[3];
+              }
+            }
+          }
+      }
+      if constexpr (STATS) {
+        const int vr = min(G::TH, a.Ho - h0), vc = min(G::TW, a.Wo - w0);
+        const float cnt = 2.0f * (float)(vr * vc);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+#pragma unroll
+          for (int o = 1; o < 32; o <<= 1) {
+            s_lo[k] += __shfl_xor(s_lo[k], o);
+            s_hi[k] += __shfl_xor(s_hi[k], o);
+          }
+          if (p32 == 0) {
+            const int g = 16 * (k >> 2) + 4 * (k & 3) + 2 * hh;
+            red[wave][g] = s_lo[k];
+            red[wave][g + 1] = s_hi[k];
+          }
+        }
+        __syncthreads();
+        if (tid < 32) gmean[tid] = (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) / cnt;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int c = k >> 2, q = k & 3;
+          const int g = 16 * c + 4 * q + 2 * hh;
+          const float ma = gmean[g], mb = gmean[g + 1];
+          float qa = 0.f, qb = 0.f;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            if (h0 + i0 + m < a.Ho && ow < a.Wo) {
+              const float d0 = a32[m][c][4 * q] - ma, d1 = a32[m][c][4 * q + 1] - ma;
+              const float d2 = a32[m][c][4 * q + 2] - mb, d3 = a32[m][c][4 * q + 3] - mb;
+              qa += d0 * d0 + d1 * d1;
+              qb += d2 * d2 + d3 * d3;
+            }
+          }
+          s_lo[k] = qa;
+          s_hi[k] = qb;
+#pragma unroll
+          for (int o = 1; o < 32; o <<= 1) {
+            s_lo[k] += __shfl_xor(s_lo[k], o);
+            s_hi[k] += __shfl_xor(s_hi[k], o);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (p32 == 0) {
+            const int g = 16 * (k >> 2) + 4 * (k & 3) + 2 * hh;
+            red[wave][g] = s_lo[k];
+            red[wave][g + 1] = s_hi[k];
+          }
+        }
+        __syncthreads();
+        if (tid < 32) {
+          const float m2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+          const int tiles = a.tiles_h * a.tiles_w;
+          a.stats[(((size_t)n * a.To + to) * tiles + (size_t)th * a.tiles_w + tw) * 32 + tid] =
+              make_float4(cnt, gmean[tid], m2, 0.f);
+        }
+      }
+      return;
+    }
+  }
 
   if constexpr (MODE == CM_I2C) {
     // pixels and all the weights once, then every K chunk without further staging
