@@ -231,6 +231,8 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
   __shared__ uint4 lds_wi[WQI];
   __shared__ float red[kWaves][32];
   __shared__ float gmean[32];
+  __shared__ float lds_bias[NT];
+  __shared__ float lds_wsc[F8 ? NT : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -247,6 +249,16 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
   const int th = v % a.tiles_h; v /= a.tiles_h;
   const int n = v;
   const int h0 = th * G::TH, w0 = tw * G::TW;
+
+  // This tile's per-channel bias (fp8: and weight scale) in LDS.  The
+  // epilogue reads them between its output stores; global reads there would
+  // each wait for the preceding stores (the output is not known not to alias).
+  if (tid < NT) {
+    const int c = ct * NT + tid;
+    lds_bias[tid] = c < a.Cout ? a.bias[c] : 0.f;
+    if constexpr (F8) lds_wsc[tid] = c < a.Cout ? a.wscale[c] : 0.f;
+  }
+  __syncthreads();
 
   f32x4 acc[MB][NB];
 #pragma unroll
@@ -601,11 +613,31 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     const int ow = w0 + j0;
     if constexpr (OUT_KIND == OUT_FP8) {
       const int res_chunks = a.Cout / OO::CH;
+      const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
+      // every residual value of this lane, loaded before the first store
+      uint2 rres[RESID ? 4 : 1][2][4];
+      if constexpr (RESID) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int oh = h0 + i0 + m;
+          const size_t pos = (size_t)oh * a.Wo + ow;
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
+              rres[m][c][q] = make_uint2(0u, 0u);
+              if (oh < a.Ho && ow < a.Wo)
+                rres[m][c][q] = *reinterpret_cast<const uint2*>(
+                    reinterpret_cast<const char*>(a.resid) +
+                    ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
+            }
+        }
+      }
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int oh = h0 + i0 + m;
         const bool valid = (oh < a.Ho) && (ow < a.Wo);
-        const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
         const size_t pos = (size_t)oh * a.Wo + ow;
         float v[2][16];
         float am[2] = {0.f, 0.f};
@@ -613,17 +645,13 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
+            const int lc = 32 * c + 8 * q + 4 * hh;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[c][4 * q + r] = a32[m][c][4 * q + r] * a.wscale[c0 + r] + a.bias[c0 + r];
+            for (int r = 0; r < 4; ++r) v[c][4 * q + r] = a32[m][c][4 * q + r] * lds_wsc[lc + r] + lds_bias[lc + r];
             if constexpr (RESID) {
-              if (valid) {
-                const uint2 rv = *reinterpret_cast<const uint2*>(
-                    reinterpret_cast<const char*>(a.resid) +
-                    ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
-                v[c][4 * q] += bf16_lo(rv.x); v[c][4 * q + 1] += bf16_hi(rv.x);
-                v[c][4 * q + 2] += bf16_lo(rv.y); v[c][4 * q + 3] += bf16_hi(rv.y);
-              }
+              const uint2 rv = rres[m][c][q];
+              v[c][4 * q] += bf16_lo(rv.x); v[c][4 * q + 1] += bf16_hi(rv.x);
+              v[c][4 * q + 2] += bf16_lo(rv.y); v[c][4 * q + 3] += bf16_hi(rv.y);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) am[c] = fmaxf(am[c], fabsf(v[c][4 * q + r]));
@@ -654,24 +682,41 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
       float s_lo[8], s_hi[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) s_lo[k] = s_hi[k] = 0.f;
+      auto out_off = [&](int m, int c, int q) {
+        const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
+        const int chunk = c0 / OO::CH, within = c0 % OO::CH;
+        return (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
+               ((size_t)(h0 + i0 + m) * a.Wo + ow) * kChunkBytes + (size_t)within * 2;
+      };
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int oh = h0 + i0 + m;
         const bool valid = (oh < a.Ho) && (ow < a.Wo);
+        // the row's residual values, loaded before its first store (one row
+        // at a time: the statistics keep every output value in registers)
+        uint2 rres[2][4];
+        if constexpr (RESID) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              rres[c][q] = make_uint2(0u, 0u);
+              if (valid)
+                rres[c][q] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + out_off(m, c, q));
+            }
+        }
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
+            const int lc = 32 * c + 8 * q + 4 * hh;
             float v4[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v4[r] = a32[m][c][4 * q + r] * a.wscale[c0 + r] + a.bias[c0 + r];
-            const int chunk = c0 / OO::CH, within = c0 % OO::CH;
-            const size_t off = (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
-                               ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * 2;
+            for (int r = 0; r < 4; ++r) v4[r] = a32[m][c][4 * q + r] * lds_wsc[lc + r] + lds_bias[lc + r];
+            const size_t off = out_off(m, c, q);
             if (valid) {
               if constexpr (RESID) {
-                const uint2 rv = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + off);
+                const uint2 rv = rres[c][q];
                 v4[0] += bf16_lo(rv.x); v4[1] += bf16_hi(rv.x);
                 v4[2] += bf16_lo(rv.y); v4[3] += bf16_hi(rv.y);
               }
@@ -794,29 +839,45 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     // and b = 2, 3 of this tile), from the block maximum over the 4 lanes
     // (g4) that hold the position's channels.  Residual (bf16) added first.
     const int res_chunks = a.Cout / OO::CH;
+    const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
+    // every residual value of this lane, loaded before the first store
+    uint2 rres[RESID ? MB : 1][NB];
+    if constexpr (RESID) {
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        int i, j;
+        out_local<MODE>(wave, m, l16, &i, &j);
+        const int oh = h0 + i, ow = w0 + j;
+        const size_t pos = (size_t)oh * a.Wo + ow;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int c0 = ct * NT + b * 16 + 4 * g4;
+          rres[m][b] = make_uint2(0u, 0u);
+          if (oh < a.Ho && ow < a.Wo)
+            rres[m][b] = *reinterpret_cast<const uint2*>(
+                reinterpret_cast<const char*>(a.resid) +
+                ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
+        }
+      }
+    }
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
       int i, j;
       out_local<MODE>(wave, m, l16, &i, &j);
       const int oh = h0 + i, ow = w0 + j;
       const bool valid = (oh < a.Ho) && (ow < a.Wo);
-      const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
       const size_t pos = (size_t)oh * a.Wo + ow;
       float v[NB][4];
       float am[2] = {0.f, 0.f};
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int c0 = ct * NT + b * 16 + 4 * g4;
+        const int lc = b * 16 + 4 * g4;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[b][r] = acc[m][b][r] * a.wscale[c0 + r] + a.bias[c0 + r];
+        for (int r = 0; r < 4; ++r) v[b][r] = acc[m][b][r] * lds_wsc[lc + r] + lds_bias[lc + r];
         if constexpr (RESID) {
-          if (valid) {
-            const uint2 rv = *reinterpret_cast<const uint2*>(
-                reinterpret_cast<const char*>(a.resid) +
-                ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
-            v[b][0] += bf16_lo(rv.x); v[b][1] += bf16_hi(rv.x);
-            v[b][2] += bf16_lo(rv.y); v[b][3] += bf16_hi(rv.y);
-          }
+          const uint2 rv = rres[m][b];
+          v[b][0] += bf16_lo(rv.x); v[b][1] += bf16_hi(rv.x);
+          v[b][2] += bf16_lo(rv.y); v[b][3] += bf16_hi(rv.y);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) am[b >> 1] = fmaxf(am[b >> 1], fabsf(v[b][r]));
@@ -844,6 +905,32 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     return;
   }
 
+  // activation output: byte offset of this lane's 4 channels of block b at
+  // position block m (the residual has the output's layout)
+  auto act_off = [&](int m, int b) {
+    int i, j;
+    out_local<MODE>(wave, m, l16, &i, &j);
+    const int c0 = ct * NT + b * 16 + 4 * g4;
+    const int chunk = c0 / OO::CH, within = c0 % OO::CH;
+    return (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
+           ((size_t)(h0 + i) * a.Wo + (w0 + j)) * kChunkBytes + (size_t)within * (kChunkBytes / OO::CH);
+  };
+  // bf16 residual: every value of this lane loaded before the first store
+  constexpr bool RPRE = RESID && OUT_KIND == OUT_ACT && OPREC == P_BF16;
+  uint2 rres[RPRE ? MB : 1][NB];
+  if constexpr (RPRE) {
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      int i, j;
+      out_local<MODE>(wave, m, l16, &i, &j);
+      const bool valid = (h0 + i < a.Ho) && (w0 + j < a.Wo);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        rres[m][b] = make_uint2(0u, 0u);
+        if (valid) rres[m][b] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + act_off(m, b));
+      }
+    }
+  }
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     int i, j;
@@ -852,22 +939,24 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     const bool valid = (oh < a.Ho) && (ow < a.Wo);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int c0 = ct * NT + b * 16 + 4 * g4;
+      const int c0 = ct * NT + b * 16 + 4 * g4, lc = b * 16 + 4 * g4;
       float v4[4];
+      // (bias and weight scale are 0 past Cout; fp8 still forces those values to 0)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const bool cv = (c0 + r) < a.Cout;
-        if constexpr (F8) v4[r] = cv ? acc[m][b][r] * a.wscale[c0 + r] + a.bias[c0 + r] : 0.f;
-        else v4[r] = acc[m][b][r] + (cv ? a.bias[c0 + r] : 0.f);
+        if constexpr (F8) {
+          const float y = acc[m][b][r] * lds_wsc[lc + r] + lds_bias[lc + r];
+          v4[r] = (c0 + r) < a.Cout ? y : 0.f;
+        } else {
+          v4[r] = acc[m][b][r] + lds_bias[lc + r];
+        }
       }
       if constexpr (OUT_KIND == OUT_ACT) {
-        const int chunk = c0 / OO::CH, within = c0 % OO::CH;
-        const size_t off = (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
-                           ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * (kChunkBytes / OO::CH);
+        const size_t off = act_off(m, b);
         if constexpr (OPREC == P_BF16) {
           if (valid) {
             if constexpr (RESID) {
-              const uint2 rv = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + off);
+              const uint2 rv = rres[m][b];
               v4[0] += bf16_lo(rv.x); v4[1] += bf16_hi(rv.x);
               v4[2] += bf16_lo(rv.y); v4[3] += bf16_hi(rv.y);
             }
