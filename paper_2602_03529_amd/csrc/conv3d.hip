@@ -87,7 +87,7 @@ constexpr bool kS1Tall = TOK_S1_TALL != 0;
 
 // Workgroups per CU the bf16 first-layer kernel is compiled for.
 #ifndef TOK_I2C_OCC
-#define TOK_I2C_OCC 3
+#define TOK_I2C_OCC 2
 #endif
 constexpr int kI2cOcc = TOK_I2C_OCC;
 
