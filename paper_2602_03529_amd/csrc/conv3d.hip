@@ -614,23 +614,22 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     if constexpr (OUT_KIND == OUT_FP8) {
       const int res_chunks = a.Cout / OO::CH;
       const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
-      // every residual value of this lane, loaded before the first store
+      // every residual value of this lane, loaded before the first store and
+      // without branches (positions past the frame edge read a clamped,
+      // in-frame address; their values are never stored)
       uint2 rres[RESID ? 4 : 1][2][4];
       if constexpr (RESID) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const int oh = h0 + i0 + m;
-          const size_t pos = (size_t)oh * a.Wo + ow;
+          const size_t pos = (size_t)min(h0 + i0 + m, a.Ho - 1) * a.Wo + min(ow, a.Wo - 1);
 #pragma unroll
           for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
-              rres[m][c][q] = make_uint2(0u, 0u);
-              if (oh < a.Ho && ow < a.Wo)
-                rres[m][c][q] = *reinterpret_cast<const uint2*>(
-                    reinterpret_cast<const char*>(a.resid) +
-                    ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
+              rres[m][c][q] = *reinterpret_cast<const uint2*>(
+                  reinterpret_cast<const char*>(a.resid) +
+                  ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
             }
         }
       }
@@ -682,28 +681,27 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
       float s_lo[8], s_hi[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) s_lo[k] = s_hi[k] = 0.f;
-      auto out_off = [&](int m, int c, int q) {
+      auto out_off = [&](int oh, int owp, int c, int q) {
         const int c0 = ct * NT + 32 * c + 8 * q + 4 * hh;
         const int chunk = c0 / OO::CH, within = c0 % OO::CH;
         return (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
-               ((size_t)(h0 + i0 + m) * a.Wo + ow) * kChunkBytes + (size_t)within * 2;
+               ((size_t)oh * a.Wo + owp) * kChunkBytes + (size_t)within * 2;
       };
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int oh = h0 + i0 + m;
         const bool valid = (oh < a.Ho) && (ow < a.Wo);
         // the row's residual values, loaded before its first store (one row
-        // at a time: the statistics keep every output value in registers)
+        // at a time: the statistics keep every output value in registers),
+        // without branches: past the frame edge from a clamped in-frame address
         uint2 rres[2][4];
         if constexpr (RESID) {
 #pragma unroll
           for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              rres[c][q] = make_uint2(0u, 0u);
-              if (valid)
-                rres[c][q] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + out_off(m, c, q));
-            }
+            for (int q = 0; q < 4; ++q)
+              rres[c][q] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) +
+                                                           out_off(min(oh, a.Ho - 1), min(ow, a.Wo - 1), c, q));
         }
 #pragma unroll
         for (int c = 0; c < 2; ++c)
@@ -713,7 +711,7 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
             float v4[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) v4[r] = a32[m][c][4 * q + r] * lds_wsc[lc + r] + lds_bias[lc + r];
-            const size_t off = out_off(m, c, q);
+            const size_t off = out_off(oh, ow, c, q);
             if (valid) {
               if constexpr (RESID) {
                 const uint2 rv = rres[c][q];
@@ -840,23 +838,21 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     // (g4) that hold the position's channels.  Residual (bf16) added first.
     const int res_chunks = a.Cout / OO::CH;
     const size_t frame = (size_t)n * a.To_buf + a.out_f0 + to;
-    // every residual value of this lane, loaded before the first store
+    // every residual value of this lane, loaded before the first store and
+    // without branches (past the frame edge: a clamped in-frame address)
     uint2 rres[RESID ? MB : 1][NB];
     if constexpr (RESID) {
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
         int i, j;
         out_local<MODE>(wave, m, l16, &i, &j);
-        const int oh = h0 + i, ow = w0 + j;
-        const size_t pos = (size_t)oh * a.Wo + ow;
+        const size_t pos = (size_t)min(h0 + i, a.Ho - 1) * a.Wo + min(w0 + j, a.Wo - 1);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int c0 = ct * NT + b * 16 + 4 * g4;
-          rres[m][b] = make_uint2(0u, 0u);
-          if (oh < a.Ho && ow < a.Wo)
-            rres[m][b] = *reinterpret_cast<const uint2*>(
-                reinterpret_cast<const char*>(a.resid) +
-                ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
+          rres[m][b] = *reinterpret_cast<const uint2*>(
+              reinterpret_cast<const char*>(a.resid) +
+              ((frame * res_chunks + c0 / OO::CH) * plane_out + pos) * kChunkBytes + (c0 % OO::CH) * 2);
         }
       }
     }
@@ -907,15 +903,15 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
 
   // activation output: byte offset of this lane's 4 channels of block b at
   // position block m (the residual has the output's layout)
-  auto act_off = [&](int m, int b) {
-    int i, j;
-    out_local<MODE>(wave, m, l16, &i, &j);
+  auto act_off = [&](int oh, int ow, int b) {
     const int c0 = ct * NT + b * 16 + 4 * g4;
     const int chunk = c0 / OO::CH, within = c0 % OO::CH;
     return (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
-           ((size_t)(h0 + i) * a.Wo + (w0 + j)) * kChunkBytes + (size_t)within * (kChunkBytes / OO::CH);
+           ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * (kChunkBytes / OO::CH);
   };
-  // bf16 residual: every value of this lane loaded before the first store
+  // bf16 residual: every value of this lane loaded before the first store,
+  // without branches (past the frame edge: a clamped in-frame address whose
+  // value is never stored)
   constexpr bool RPRE = RESID && OUT_KIND == OUT_ACT && OPREC == P_BF16;
   uint2 rres[RPRE ? MB : 1][NB];
   if constexpr (RPRE) {
@@ -923,12 +919,10 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     for (int m = 0; m < MB; ++m) {
       int i, j;
       out_local<MODE>(wave, m, l16, &i, &j);
-      const bool valid = (h0 + i < a.Ho) && (w0 + j < a.Wo);
+      const int ohc = min(h0 + i, a.Ho - 1), owc = min(w0 + j, a.Wo - 1);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        rres[m][b] = make_uint2(0u, 0u);
-        if (valid) rres[m][b] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + act_off(m, b));
-      }
+      for (int b = 0; b < NB; ++b)
+        rres[m][b] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.resid) + act_off(ohc, owc, b));
     }
   }
 #pragma unroll
@@ -952,7 +946,7 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
         }
       }
       if constexpr (OUT_KIND == OUT_ACT) {
-        const size_t off = act_off(m, b);
+        const size_t off = act_off(oh, ow, b);
         if constexpr (OPREC == P_BF16) {
           if (valid) {
             if constexpr (RESID) {
