@@ -25,8 +25,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Mean HBM bytes per launch of the level-0 residual-block conv at 4 x 17 x
 # 1280x720 BF16, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled
 # by the same counters on a 1 GiB device copy; see profiles/.  Valid for that
-# workload and the conv kernel as measured; other shapes report null.
-RB_CONV_HBM_BYTES_720P = 31.30e9
+# workload and the conv kernel as measured; other shapes report null, and so
+# does this one while the kernel has changed since the counters were taken.
+RB_CONV_HBM_BYTES_720P = None
 F32_PEAK_TFLOPS = 157.3
 # FLOPs per output position of each conv (2 * 27 * Cin * Cout, 1x1x1: 2 * Cin * Cout) and the level it runs at.
 CONV_FLOPS = {
