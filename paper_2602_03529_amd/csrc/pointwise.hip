@@ -331,6 +331,12 @@ __device__ __forceinline__ void store_fp8_block(const float* v, uint8_t* dst, ui
 
 // y = silu(x * scale + shift): bf16 level-0 activations (64 channels, 2
 // chunks of 32) -> MX-FP8 (1 chunk of 64 + 2 scale bytes per position).
+// Eight lanes per position: lanes 0-3 hold the four 8-channel quads of input
+// chunk 0 (output channels 0-31, the first MX block), lanes 4-7 those of chunk
+// 1; a block's maximum is reduced over its 4 lanes by shuffles, and lane 0
+// stores both scale bytes.  Each thread keeps its 8 channels' scale and shift
+// in registers for kF8Items positions, 32 positions apart.
+constexpr int kF8Items = 4;
 __global__ void __launch_bounds__(256) gn_act_fp8_kernel(const uint4* __restrict__ in, int in_Tb, int in_f0,
                                                           uint8_t* __restrict__ out, uint8_t* __restrict__ osc,
                                                           int out_Tb, int out_f0, int F, int HW,
@@ -338,26 +344,47 @@ __global__ void __launch_bounds__(256) gn_act_fp8_kernel(const uint4* __restrict
                                                           const float* __restrict__ shift) {
   const int nf = blockIdx.y;  // (n, f)
   const int n = nf / F, f = nf % F;
-  const int t = blockIdx.x * 256 + threadIdx.x;  // (position, block)
-  if (t >= HW * 2) return;
-  const int pos = t >> 1, blk = t & 1;
+  const int sub = threadIdx.x & 7, blk = sub >> 2, qq = sub & 3;
   const size_t fin = (size_t)n * in_Tb + in_f0 + f, fout = (size_t)n * out_Tb + out_f0 + f;
-  const uint4* src = in + ((fin * 2 + blk) * HW + pos) * 4;
-  const float* sc = scale + (size_t)nf * 64 + blk * 32;
-  const float* sh = shift + (size_t)nf * 64 + blk * 32;
-  float v[32];
+  const int c0 = blk * 32 + qq * 8;
+  const float4* ps = reinterpret_cast<const float4*>(scale + (size_t)nf * 64 + c0);
+  const float4* ph = reinterpret_cast<const float4*>(shift + (size_t)nf * 64 + c0);
+  const float4 s0 = ps[0], s1 = ps[1], h0 = ph[0], h1 = ph[1];
+  const float sc[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+  const float sh[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+  const int p0 = blockIdx.x * (32 * kF8Items) + (threadIdx.x >> 3);
+  const uint4* src = in + (fin * 2 + blk) * (size_t)HW * 4 + qq;
+  uint4 u[kF8Items];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint4 u = src[q];
-    const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+  for (int k = 0; k < kF8Items; ++k) {
+    const int pos = p0 + 32 * k;
+    u[k] = pos < HW ? src[(size_t)pos * 4] : make_uint4(0u, 0u, 0u, 0u);
+  }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = q * 8 + 2 * k;
-      v[c] = silu_f(bf16_lo(w4[k]) * sc[c] + sh[c]);
-      v[c + 1] = silu_f(bf16_hi(w4[k]) * sc[c + 1] + sh[c + 1]);
+  for (int k = 0; k < kF8Items; ++k) {
+    const int pos = p0 + 32 * k;
+    const uint32_t w4[4] = {u[k].x, u[k].y, u[k].z, u[k].w};
+    float v[8];
+    float am = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[2 * j] = silu_f(bf16_lo(w4[j]) * sc[2 * j] + sh[2 * j]);
+      v[2 * j + 1] = silu_f(bf16_hi(w4[j]) * sc[2 * j + 1] + sh[2 * j + 1]);
+      am = fmaxf(am, fmaxf(fabsf(v[2 * j]), fabsf(v[2 * j + 1])));
+    }
+    am = fmaxf(am, __shfl_xor(am, 1));
+    am = fmaxf(am, __shfl_xor(am, 2));
+    const int e = fp8_block_exp(am);
+    const int e_other = __shfl_xor(e, 4);  // the other block's exponent (lane 0: block 1's)
+    const float fs = ldexpf(1.0f, -e);
+    if (pos < HW) {
+      const uint2 o = make_uint2(pack_fp8x4(v[0] * fs, v[1] * fs, v[2] * fs, v[3] * fs),
+                                 pack_fp8x4(v[4] * fs, v[5] * fs, v[6] * fs, v[7] * fs));
+      *reinterpret_cast<uint2*>(out + (fout * HW + pos) * kChunkBytes + c0) = o;
+      if (sub == 0)
+        reinterpret_cast<uint16_t*>(osc)[fout * HW + pos] = (uint16_t)((e + 127) | ((e_other + 127) << 8));
     }
   }
-  store_fp8_block(v, out + (fout * HW + pos) * kChunkBytes + blk * 32, osc + (fout * HW + pos) * 2 + blk);
 }
 
 // codes (6) -> 128 channels of MX-FP8 (2 chunks, 4 scale bytes per position).
@@ -427,7 +454,7 @@ hipError_t launch_gn_act_fp8(const void* in, int in_Tb, int in_f0, uint8_t* out,
   const long long frames = (long long)N * F;
   if (frames > 65535 || F < 1 || in_f0 < 0 || in_f0 + F > in_Tb || out_f0 < 0 || out_f0 + F > out_Tb)
     return hipErrorInvalidValue;
-  const dim3 grid(blocks_for((size_t)HW * 2, 256), (unsigned)frames);
+  const dim3 grid(blocks_for((size_t)HW, 32 * kF8Items), (unsigned)frames);
   hipLaunchKernelGGL(gn_act_fp8_kernel, grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(in), in_Tb, in_f0, out,
                      out_scale, out_Tb, out_f0, F, HW, scale, shift);
   return hipGetLastError();
