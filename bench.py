@@ -373,7 +373,7 @@ def main():
     # in + out per launch, plus the residual read on the 4 second convs of the 8
     rb_io_bytes = pos[0] * 64 * 2 * 2 + pos[0] * 64 * 2 // 2
     rb_traffic = RB_CONV_HBM_BYTES_720P if (N, T, H, W) == (4, 17, 720, 1280) else None
-    roofline = dict(kernel="level-0 residual-block conv 64->64 (bf16 MFMA, GN+SiLU prologue)", bound="mfma",
+    roofline = dict(kernel="level-0 residual-block conv 64->64 (bf16 MFMA; bias, residual and GN-statistics epilogue)", bound="mfma",
                     achieved=round(achieved, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / BF16_PEAK_TFLOPS, 4), traffic=rb_traffic,
                     traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
