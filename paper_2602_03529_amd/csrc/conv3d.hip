@@ -1296,6 +1296,22 @@ __device__ __forceinline__ void transpose8x8_bf16(const uint4* v, uint4* w) {
   }
 }
 
+// The same transpose, handing each w[c] to store(c, w[c]) as soon as it is
+// formed (no 8-vector temporary).
+template <typename F>
+__device__ __forceinline__ void transpose8x8_bf16_store(const uint4* v, F store) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    uint32_t d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a = (&v[2 * j].x)[c >> 1], b = (&v[2 * j + 1].x)[c >> 1];
+      d[j] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+    }
+    store(c, make_uint4(d[0], d[1], d[2], d[3]));
+  }
+}
+
 // 16 bf16 from element offset e0 (a multiple of 8) of an LDS array: two
 // aligned 16-byte reads, from which the 8 elements at offset 0, 1 or 2 are
 // taken in registers (no unaligned LDS access).
@@ -1359,56 +1375,76 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
     if constexpr (VIEW == CM_S1) ts = max(to + kt - 2, 0);
     else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
     else ts = (max(to + kt - 2, 0) + 1) >> 1;
-    __syncthreads();
-    // ---- stage dy: blocks of 8 positions x 8 output channels (position block
-    // fastest across lanes: their transposed 16-byte stores hit distinct banks) ----
-    for (int blk = tid; blk < (NPOS / 8) * 8; blk += 256) {
-      const int pb = blk % (NPOS / 8), cb = blk / (NPOS / 8);
-      uint4 vv[8], ww[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int p = pb * 8 + k;
-        const int oh = h0 + p / 64, ow = w0 + p % 64;
-        const int oc = ot * 64 + cb * 8;  // 8 channels inside one 32-channel chunk
-        vv[k] = make_uint4(0, 0, 0, 0);
-        if (oh < a.Ho && ow < a.Wo && oc < dy_ch)
-          vv[k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + oc / 32) * plane_y + (size_t)oh * a.Wo + ow) * 4 +
-                      (oc % 32) / 8];
-      }
-      transpose8x8_bf16(vv, ww);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) *reinterpret_cast<uint4*>(&s_dy[(cb * 8 + k) * Lp::DYS + pb * 8]) = ww[k];
-    }
-    // ---- stage the input halo: blocks of 8 columns (of one plane row) x 8 input channels ----
+    // ---- staging: dy in blocks of 8 positions x 8 output channels (position
+    // block fastest across lanes: their transposed 16-byte stores hit distinct
+    // banks), the input halo in blocks of 8 columns (of one plane row) x 8
+    // input channels.  Thread t owns blocks t and t + 256 of the NDY + NHX and
+    // issues all their global loads before the barrier, so an item waits for
+    // one load latency, overlapped with the other waves' previous compute.
     constexpr int QB = 9;  // column blocks holding the 66 halo columns
-    for (int blk = tid; blk < G::ROWS * G::PLANES * QB * 8; blk += 256) {
-      int r = blk;
-      const int qb = r % QB; r /= QB;
-      const int cb = r % 8; r /= 8;
-      const int pl = r % G::PLANES; r /= G::PLANES;
-      const int hr = r;
-      uint4 vv[8], ww[8];
+    constexpr int NDY = (NPOS / 8) * 8, NHX = G::ROWS * G::PLANES * QB * 8;
+    static_assert(NDY + NHX <= 512, "two staging blocks per thread");
+    auto halo_block = [&](int hb, int* qb, int* cb, int* pl, int* hr) {
+      *qb = hb % QB; hb /= QB;
+      *cb = hb % 8; hb /= 8;
+      *pl = hb % G::PLANES;
+      *hr = hb / G::PLANES;
+    };
+    uint4 vv[2][8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int q = qb * 8 + k;
-        int hs, ws;
-        if constexpr (VIEW == CM_S1) { hs = h0 - 1 + hr; ws = w0 - 1 + q; }
-        else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + hr; ws = 2 * w0 - 1 + 2 * q + pl; }
-        else {  // upsampled coordinates -> source
-          const int hu = h0 - 1 + hr, wu = w0 - 1 + q;
-          hs = hu < 0 ? -1 : hu >> 1;
-          ws = wu < 0 ? -1 : wu >> 1;
+    for (int r2 = 0; r2 < 2; ++r2) {
+      const int blk = tid + 256 * r2;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) vv[r2][k] = make_uint4(0, 0, 0, 0);
+      if (blk < NDY) {
+        const int pb = blk % (NPOS / 8), cb = blk / (NPOS / 8);
+        const int oc = ot * 64 + cb * 8;  // 8 channels inside one 32-channel chunk
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int p = pb * 8 + k;
+          const int oh = h0 + p / 64, ow = w0 + p % 64;
+          if (oh < a.Ho && ow < a.Wo && oc < dy_ch)
+            vv[r2][k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + oc / 32) * plane_y + (size_t)oh * a.Wo + ow) * 4 +
+                            (oc % 32) / 8];
         }
+      } else if (blk < NDY + NHX) {
+        int qb, cb, pl, hr;
+        halo_block(blk - NDY, &qb, &cb, &pl, &hr);
         const int ic = it * 64 + cb * 8;
-        vv[k] = make_uint4(0, 0, 0, 0);
-        if (q < 66 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ic < x_ch)
-          vv[k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ic / 32) * plane_x + (size_t)hs * a.Wi + ws) * 4 +
-                     (ic % 32) / 8];
-      }
-      transpose8x8_bf16(vv, ww);
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        *reinterpret_cast<uint4*>(&s_x[(cb * 8 + k) * Lp::XS + (hr * G::PLANES + pl) * kWmCols + qb * 8]) = ww[k];
+        for (int k = 0; k < 8; ++k) {
+          const int q = qb * 8 + k;
+          int hs, ws;
+          if constexpr (VIEW == CM_S1) { hs = h0 - 1 + hr; ws = w0 - 1 + q; }
+          else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + hr; ws = 2 * w0 - 1 + 2 * q + pl; }
+          else {  // upsampled coordinates -> source
+            const int hu = h0 - 1 + hr, wu = w0 - 1 + q;
+            hs = hu < 0 ? -1 : hu >> 1;
+            ws = wu < 0 ? -1 : wu >> 1;
+          }
+          if (q < 66 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ic < x_ch)
+            vv[r2][k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ic / 32) * plane_x + (size_t)hs * a.Wi + ws) * 4 +
+                           (ic % 32) / 8];
+        }
+      }
+    }
+    __syncthreads();  // every wave is done with the previous item's LDS tiles
+#pragma unroll
+    for (int r2 = 0; r2 < 2; ++r2) {
+      const int blk = tid + 256 * r2;
+      if (blk < NDY) {
+        const int pb = blk % (NPOS / 8), cb = blk / (NPOS / 8);
+        transpose8x8_bf16_store(vv[r2], [&](int k, const uint4& w) {
+          *reinterpret_cast<uint4*>(&s_dy[(cb * 8 + k) * Lp::DYS + pb * 8]) = w;
+        });
+      } else if (blk < NDY + NHX) {
+        int qb, cb, pl, hr;
+        halo_block(blk - NDY, &qb, &cb, &pl, &hr);
+        uint16_t* dst = &s_x[cb * 8 * Lp::XS + (hr * G::PLANES + pl) * kWmCols + qb * 8];
+        transpose8x8_bf16_store(vv[r2], [&](int k, const uint4& w) {
+          *reinterpret_cast<uint4*>(dst + k * Lp::XS) = w;
+        });
+      }
     }
     __syncthreads();
     if (bias_sum) {
