@@ -1564,6 +1564,8 @@ hipError_t dispatch_fp8(const ConvLaunch& a, hipStream_t s) {
 
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
   if (a.stats && !(a.nt == 64 && a.Cout == 64 && a.cout_tiles == 1)) return hipErrorInvalidValue;
+  // the epilogue reads the residual of every channel of its tile
+  if (a.resid && (a.nt <= 0 || a.Cout % a.nt != 0)) return hipErrorInvalidValue;
   if (a.prec == P_BF16) return dispatch_prec<P_BF16>(a, s);
   if (a.prec == P_F32) return dispatch_prec<P_F32>(a, s);
   if (a.prec == P_FP8) return dispatch_fp8(a, s);
