@@ -9,11 +9,11 @@ namespace tok {
 namespace {
 
 // ---------------------------------------------------------------------------
-// GroupNorm finalize.  One block per frame (n, t); 32 groups x 8 lanes.
-// Lane j of group g merges tiles j, j+8, ... with Chan's pairwise update,
-// then the 8 lane results are merged in a fixed butterfly order, so the
-// result is deterministic and independent of the launch order of the
-// producing conv's workgroups.
+// GroupNorm finalize.  One wave per (frame (n, t), group), four groups per
+// block, eight blocks per frame.  Lane j of group g merges tiles j, j+64, ...
+// with Chan's pairwise update, then the 64 lane results are merged in a fixed
+// butterfly order, so the result is deterministic and independent of the
+// launch order of the producing conv's workgroups.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void chan_merge(float& n, float& m, float& q, float nb, float mb, float qb) {
   if (nb == 0.f) return;
@@ -32,16 +32,17 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
                                                            float* __restrict__ scale,
                                                            float* __restrict__ shift,
                                                            float2* __restrict__ mr) {
-  const int frame = blockIdx.x;
-  const int g = threadIdx.x >> 3, j = threadIdx.x & 7;
+  const int frame = blockIdx.x >> 3;
+  const int g = ((blockIdx.x & 7) << 2) + (threadIdx.x >> 6), j = threadIdx.x & 63;
   const float4* s = stats + (size_t)frame * tiles * 32;
   float n = 0.f, m = 0.f, q = 0.f;
-  for (int t = j; t < tiles; t += 8) {
+#pragma unroll 4
+  for (int t = j; t < tiles; t += 64) {
     const float4 p = s[(size_t)t * 32 + g];
     chan_merge(n, m, q, p.x, p.y, p.z);
   }
 #pragma unroll
-  for (int off = 4; off >= 1; off >>= 1) {
+  for (int off = 32; off >= 1; off >>= 1) {
     const float nb = __shfl_xor(n, off), mb = __shfl_xor(m, off), qb = __shfl_xor(q, off);
     // lower lane keeps itself as the left operand: same order on every lane pair
     if ((j & off) == 0) chan_merge(n, m, q, nb, mb, qb);
@@ -428,7 +429,8 @@ inline unsigned blocks_for(size_t n, int per) { return (unsigned)((n + per - 1) 
 
 hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const float* gamma, const float* beta,
                               float eps, float* scale, float* shift, float2* mr, hipStream_t s) {
-  hipLaunchKernelGGL(gn_finalize_kernel, dim3(frames), dim3(256), 0, s, stats, tiles, gamma, beta, eps, scale,
+  if (frames < 1 || frames > (1 << 27)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gn_finalize_kernel, dim3(frames * 8), dim3(256), 0, s, stats, tiles, gamma, beta, eps, scale,
                      shift, mr);
   return hipGetLastError();
 }
