@@ -1505,6 +1505,8 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
 
 // Sums the per-split partials in split order: weights into the canonical
 // [o][i][kt][kh][kw] layout, then (elements past the weights) the bias.
+// Thread e takes element e of a split's [kt][kh*3+kw][o][i] partial, so the
+// loads of a wave are contiguous; only the one store per element is strided.
 __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ partial,
                                                             const float* __restrict__ bpartial, int splits, int Cout,
                                                             int Cin, float* __restrict__ dw, float* __restrict__ db) {
@@ -1514,19 +1516,18 @@ __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restri
     const size_t o = e - total;
     if (o >= (size_t)Cout || !db) return;
     float acc = 0.f;
+#pragma unroll 8
     for (int s = 0; s < splits; ++s) acc += bpartial[(size_t)s * Cout + o];
     db[o] = acc;
     return;
   }
-  const int tap = (int)(e % 27);
-  const size_t oi = e / 27;
-  const int o = (int)(oi / Cin), i = (int)(oi % Cin);
-  const int kt = tap / 9, t9 = tap % 9;
-  const size_t stride = (size_t)27 * Cout * Cin;
-  const size_t base = (((size_t)kt * 9 + t9) * Cout + o) * Cin + i;
+  const int i = (int)(e % Cin);
+  const size_t r = e / Cin;
+  const int o = (int)(r % Cout), tap = (int)(r / Cout);  // tap = kt * 9 + kh * 3 + kw
   float acc = 0.f;
-  for (int s = 0; s < splits; ++s) acc += partial[(size_t)s * stride + base];
-  dw[e] = acc;
+#pragma unroll 8
+  for (int s = 0; s < splits; ++s) acc += partial[(size_t)s * total + e];
+  dw[((size_t)o * Cin + i) * 27 + tap] = acc;
 }
 
 }  // namespace
