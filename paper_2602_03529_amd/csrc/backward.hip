@@ -250,6 +250,7 @@ __global__ void __launch_bounds__(64) gn_bwd_param_kernel(const float2* __restri
                                                            float* __restrict__ dgamma, float* __restrict__ dbeta) {
   const int c = threadIdx.x;
   float a = 0.f, b = 0.f;
+#pragma unroll 8
   for (int f = 0; f < frames; ++f) {
     const float2 v = fsum[(size_t)f * 64 + c];
     a += v.x;
@@ -426,16 +427,27 @@ __global__ void __launch_bounds__(256) outer6_kernel(const float* __restrict__ a
   }
 }
 
-// Sums the block partials in block order.  transposed = 0: dw[k][c] (a 128 -> 6
-// projection, whose bias gradient is A); transposed = 1: dw[c][k] (6 -> 128,
-// bias gradient X).
-__global__ void __launch_bounds__(256) outer6_reduce_kernel(const float* __restrict__ partial, int rows,
-                                                             int transposed, float* __restrict__ dw,
-                                                             float* __restrict__ db) {
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  if (o >= kOuterCols) return;
+// Sums the block partials in a fixed order: 64 columns per block, wave w
+// sums rows w, w + 16, ... in order, then the 16 wave sums are added in wave
+// order.  transposed = 0: dw[k][c] (a 128 -> 6 projection, whose bias
+// gradient is A); transposed = 1: dw[c][k] (6 -> 128, bias gradient X).
+__global__ void __launch_bounds__(1024) outer6_reduce_kernel(const float* __restrict__ partial, int rows,
+                                                              int transposed, float* __restrict__ dw,
+                                                              float* __restrict__ db) {
+  __shared__ float part[16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += partial[(size_t)r * kOuterCols + o];
+  if (o < kOuterCols) {
+#pragma unroll 8
+    for (int r = w; r < rows; r += 16) s += partial[(size_t)r * kOuterCols + o];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || o >= kOuterCols) return;
+  s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s += part[k][lane];
   if (o < 768) {
     const int k = o / 128, c = o % 128;
     dw[transposed ? c * 6 + k : o] = s;
@@ -541,7 +553,7 @@ hipError_t launch_outer6(const float* a6, const void* x, size_t ntok, int HW, in
                          int transposed, float* dw, float* db, hipStream_t s) {
   const int rows = outer6_blocks(ntok);
   TOK_PREC_LAUNCH(outer6_kernel, dim3(rows), dim3(256), a6, x, ntok, HW, partial);
-  hipLaunchKernelGGL(outer6_reduce_kernel, dim3((kOuterCols + 255) / 256), dim3(256), 0, s, partial, rows, transposed,
+  hipLaunchKernelGGL(outer6_reduce_kernel, dim3((kOuterCols + 63) / 64), dim3(1024), 0, s, partial, rows, transposed,
                      dw, db);
   return hipGetLastError();
 }
