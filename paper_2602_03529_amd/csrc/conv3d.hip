@@ -36,10 +36,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 
-#ifndef TOK_SWZ_SHIFT
-#define TOK_SWZ_SHIFT 1
-#endif
-__host__ __device__ __forceinline__ int swz(int row) { return (row >> TOK_SWZ_SHIFT) & 3; }
+__host__ __device__ __forceinline__ int swz(int row) { return (row >> 1) & 3; }
 
 template <int PREC> struct Op;
 template <> struct Op<P_F32> { static constexpr int CH = 16; static constexpr int QE = 4; };
@@ -55,10 +52,6 @@ template <> struct Geo<CM_S1> {
 };
 template <> struct Geo<CM_S2> {
   static constexpr int WR = 1, TW = 32, TH = 4, HH = 2 * TH + 1, HW = 2 * TW + 1;
-  static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
-};
-template <> struct Geo<CM_UP> {
-  static constexpr int WR = 2, TW = 64, TH = 8, HH = TH / 2 + 2, HW = TW / 2 + 2;
   static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
 template <> struct Geo<CM_S1T> : Geo<CM_S1> {};
@@ -80,22 +73,16 @@ template <> struct Geo<CM_UPF> {
 // Stride-1 modes give each wave a 4 x 32 sub-tile (waves 2 x 2 over the 8 x 64
 // workgroup tile): an activation operand loaded for halo row r then serves
 // output rows r - kh for every kh, a third fewer LDS reads than 2 x 64 rows.
-#ifndef TOK_S1_TALL
-#define TOK_S1_TALL 1
-#endif
-constexpr bool kS1Tall = TOK_S1_TALL != 0;
 
-// Workgroups per CU the bf16 first-layer kernel is compiled for.
-#ifndef TOK_I2C_OCC
-#define TOK_I2C_OCC 2
-#endif
-constexpr int kI2cOcc = TOK_I2C_OCC;
+// Workgroups per CU the bf16 first-layer kernel is compiled for (at three
+// its registers spill).
+constexpr int kI2cOcc = 2;
 
 // Output-tile-local position of lane l16 in position block m of a wave.
 template <int MODE>
 __device__ __forceinline__ void out_local(int wave, int m, int l16, int* i, int* j) {
   using G = Geo<MODE>;
-  if constexpr ((MODE == CM_S1 || MODE == CM_S1T || MODE == CM_I2C) && kS1Tall) {
+  if constexpr (MODE == CM_S1 || MODE == CM_S1T || MODE == CM_I2C) {
     *i = 4 * (wave >> 1) + (m >> 1);
     *j = 32 * (wave & 1) + 16 * (m & 1) + l16;
   } else if constexpr (MODE == CM_UPF) {
@@ -135,7 +122,7 @@ __device__ __forceinline__ void halo_src(int p, int h0, int w0, int* hs, int* ws
     const int c = (pc < G::TW + 1) ? 2 * pc : 2 * (pc - (G::TW + 1)) + 1;
     *hs = 2 * h0 - 1 + r;
     *ws = 2 * w0 - 1 + c;
-  } else {  // CM_UP, CM_UPF: source rows / columns of the upsampled tile
+  } else {  // CM_UPF: source rows / columns of the upsampled tile
     *hs = (h0 >> 1) - 1 + r;
     *ws = (w0 >> 1) - 1 + pc;
   }
@@ -200,8 +187,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + min(x, r) + l;
 }
 
-template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS, bool DB>
-__global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC == P_BF16) ? kI2cOcc : 2))
+template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS>
+__global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ? kI2cOcc : 2)
     conv3d_kernel(ConvLaunch a) {
   using G = Geo<MODE>;
   using O = Op<PREC>;
@@ -213,15 +200,14 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
   constexpr int MB = G::MB;             // position blocks per wave
   constexpr int HQ = HALO * 4;          // halo quads per stage
   constexpr int WQ = G::WT * NT * 4;    // weight quads per stage
-  constexpr int NBUF = DB ? 2 : 1;      // LDS buffers (double buffering: 1 workgroup per CU)
+  constexpr int NBUF = 1;               // LDS buffers (two workgroups per CU overlap staging and compute)
   static_assert(WQ % 64 == 0, "weight stage must be whole waves");
-  static_assert(!DB || IN_KIND == IN_ACT, "double buffering needs asynchronous staging");
-  static_assert(!F8 || (IN_KIND == IN_ACT && !DB), "fp8: activations in, single buffer");
+  static_assert(!F8 || IN_KIND == IN_ACT, "fp8: activations in");
   static_assert(OUT_KIND != OUT_FP8 || (F8 && !STATS && NB == 4), "fp8 output: fp8 kernels, no statistics");
   constexpr int SCN = F8 ? HALO : 1;      // fp8: two E8M0 bytes per halo row
 
   constexpr int PXN = MODE == CM_I2C ? 3 * (G::TH + 2) * (G::TW + 2) * 4 : 1;  // normalised pixel halo
-  static_assert(MODE != CM_I2C || (IN_KIND == IN_U8 && !DB && !F8), "im2col: uint8 input");
+  static_assert(MODE != CM_I2C || (IN_KIND == IN_U8 && !F8), "im2col: uint8 input");
 
   __shared__ uint4 lds_a[NBUF][HQ];
   __shared__ uint4 lds_w[NBUF][WQ];
@@ -283,7 +269,6 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     if constexpr (MODE == CM_S1) g = max(tg + kt - 2, 0);
     else if constexpr (MODE == CM_S1T) g = tg + kt;  // gradient frames t, t+1, t+2 (past the end: none)
     else if constexpr (MODE == CM_S2) g = max(2 * tg + kt - 2, 0);
-    else if constexpr (MODE == CM_UP) g = (max(tg + kt - 2, 0) + 1) >> 1;
     else {
       // even output frame 2j reads source frames j-1 (clamped) and j; odd 2j+1 reads j and j+1
       const int jt = tg >> 1;
@@ -465,7 +450,7 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
       }
       return;
     }
-    if constexpr ((MODE == CM_S1 || MODE == CM_S1T) && kS1Tall) {
+    if constexpr (MODE == CM_S1 || MODE == CM_S1T) {
       // per kw: the 6 halo rows x 2 column blocks this wave reads, reused for kh = 0, 1, 2
       static_assert(MB == 8, "4 x 32 wave tile");
       const int i0 = 4 * (wave >> 1), j0 = 32 * (wave & 1) + l16;
@@ -803,16 +788,6 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     for (int st = 0; st < nstages; ++st) compute_i2c(st);
-  } else if constexpr (DB) {
-    issue_async(0, 0);
-    for (int st = 0; st < nstages; ++st) {
-      // stage st has landed in buffer st & 1, and every wave is done with
-      // stage st - 1, whose buffer the next transfers overwrite
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-      if (st + 1 < nstages) issue_async(st + 1, (st + 1) & 1);
-      compute(st & 1);
-    }
   } else {
     for (int st = 0; st < nstages; ++st) {
       if constexpr (MODE == CM_S1T) {
@@ -1058,19 +1033,15 @@ __global__ void __launch_bounds__(kThreads, DB ? 1 : ((MODE == CM_I2C && PREC ==
   }
 }
 
-template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS, bool DB = false>
+template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS>
 hipError_t launch_one(const ConvLaunch& a, hipStream_t s) {
   const long long nb = (long long)a.N * a.To * a.tiles_h * a.tiles_w * a.cout_tiles;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((conv3d_kernel<PREC, MODE, NB, IN_KIND, OUT_KIND, RESID, STATS, DB>),
+  hipLaunchKernelGGL((conv3d_kernel<PREC, MODE, NB, IN_KIND, OUT_KIND, RESID, STATS>),
                      dim3((unsigned)nb), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-#ifndef TOK_CONV_DB
-#define TOK_CONV_DB 0
-#endif
-constexpr bool kDB = TOK_CONV_DB != 0;
 
 template <int PREC>
 hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
@@ -1083,35 +1054,30 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   }
   if (a.out_kind == OUT_RGB32) {
     if (a.mode == CM_S1 && a.nt == 16 && !res && !st)
-      return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false, kDB>(a, s);
+      return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
     if (a.mode == CM_S1T && a.nt == 16 && !res && !st)
-      return launch_one<PREC, CM_S1T, 1, IN_ACT, OUT_RGB32, false, false, false>(a, s);
+      return launch_one<PREC, CM_S1T, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.nt != 64) return hipErrorInvalidValue;
   if (a.mode == CM_S1) {
-    if (!res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
-    if (res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, true, kDB>(a, s);
-    if (res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, false, kDB>(a, s);
-    if (!res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
+    if (!res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, true>(a, s);
+    if (res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, true>(a, s);
+    if (res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, false>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_S2) {
-    if (!res && !st) return launch_one<PREC, CM_S2, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
-    return hipErrorInvalidValue;
-  }
-  if (a.mode == CM_UP) {
-    if (!res && !st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
-    if (!res && st) return launch_one<PREC, CM_UP, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_S2, 4, IN_ACT, OUT_ACT, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_S1T) {
-    if (!res && !st) return launch_one<PREC, CM_S1T, 4, IN_ACT, OUT_ACT, false, false, false>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_S1T, 4, IN_ACT, OUT_ACT, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_UPF) {
-    if (!res && !st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, false, kDB>(a, s);
-    if (!res && st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, true, kDB>(a, s);
+    if (!res && !st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, false>(a, s);
+    if (!res && st) return launch_one<PREC, CM_UPF, 4, IN_ACT, OUT_ACT, false, true>(a, s);
     return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;

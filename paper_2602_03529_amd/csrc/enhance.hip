@@ -190,7 +190,9 @@ hipError_t launch_residual(const uint8_t* x, const float* xhat, int N, int T, in
                            uint32_t* index, float* value, long long capacity, unsigned long long* clip_off,
                            void* ws, hipStream_t s) {
   const long long E = 3LL * H * W, bpc = (E + kRsBlock - 1) / kRsBlock;
-  if (N < 1 || N > 65535 || T < 1 || E < 16 || (E & 15) || bpc > 0x7fffffffLL) return hipErrorInvalidValue;
+  // entry counts and offsets are 32-bit: the whole batch's N E entries must fit
+  if (N < 1 || N > 65535 || T < 1 || E < 16 || (E & 15) || bpc > 0x7fffffffLL || (long long)N * E >= 0xffffffffLL)
+    return hipErrorInvalidValue;
   uint32_t* counts = static_cast<uint32_t*>(ws);
   const dim3 grid((unsigned)bpc, N);
   hipLaunchKernelGGL(rs_mean_kernel, grid, dim3(kRsThreads), 0, s, x, xhat, T, E, theta, rs, counts);

@@ -69,13 +69,7 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
 // quads of that plane, kThreads apart, so each load / store instruction is
 // fully coalesced and all quads of a thread share one channel set.
 // ---------------------------------------------------------------------------
-#ifndef TOK_ACT_ITEMS
-#define TOK_ACT_ITEMS 4
-#endif
-#ifndef TOK_ACT_NT
-#define TOK_ACT_NT 0
-#endif
-constexpr int kActItems = TOK_ACT_ITEMS;
+constexpr int kActItems = 4;
 
 template <int PREC>
 __global__ void __launch_bounds__(256) gn_act_kernel(const uint4* in, int in_Tb, int in_f0,
@@ -121,12 +115,7 @@ __global__ void __launch_bounds__(256) gn_act_kernel(const uint4* in, int in_Tb,
 #pragma unroll
       for (int j = 0; j < 4; ++j) o[j] = __float_as_uint(silu_f(fmaf(__uint_as_float(u[j]), sc[j], sh[j])));
     }
-    if constexpr (TOK_ACT_NT != 0) {
-      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-      __builtin_nontemporal_store(u32x4{o[0], o[1], o[2], o[3]}, reinterpret_cast<u32x4*>(dst + q));
-    } else {
-      dst[q] = make_uint4(o[0], o[1], o[2], o[3]);
-    }
+    dst[q] = make_uint4(o[0], o[1], o[2], o[3]);
   }
 }
 

@@ -247,6 +247,10 @@ struct tok_server {
           hipStreamSynchronize(streams[k]);
           arena.release(scratch);
           arena.release(res);
+          // the block is back in the arena: no request may keep a view of it
+          // (a later release would free it again, a wait would hand out views
+          // into whatever batch the arena gives it to next)
+          for (Request* r : cand) r->results = nullptr;
           for (Request* r : cand) finish(r, e);
           delete b;
           cv.notify_all();

@@ -209,26 +209,36 @@ def conv3d_wgrad(x: torch.Tensor, dy: torch.Tensor, shape_x, shape_y, Cin: int, 
     return dw, db
 
 
+def _load_params(model, params):
+    """Make the model hold `params` (repacking only when they changed)."""
+    key = (params.data_ptr(), params._version)
+    if getattr(model, "_params_key", None) != key:
+        model.set_weights(params.detach())
+        model._params_key = key
+
+
 class TokenizerLoss(torch.autograd.Function):
     """L(params) of the training objective with the library's hand-written
     backward: forward runs tok_train_forward (after loading `params` into the
     model when they changed), backward runs tok_backward with the incoming
     gradient as its scale.  Each call keeps its own tape (workspace) until its
-    backward has run."""
+    backward has run; the backward recomputes block interiors with the
+    weights of its own forward (reloaded if another call changed the model's
+    weights in between; autograd rejects params modified in place)."""
 
     @staticmethod
     def forward(ctx, params, model, x, keep):
-        key = (params.data_ptr(), params._version)
-        if getattr(model, "_params_key", None) != key:
-            model.set_weights(params.detach())
-            model._params_key = key
+        _load_params(model, params)
         out = model.train_forward(x, keep)
+        ctx.save_for_backward(params)
         ctx.model, ctx.x, ctx.ws = model, x, out["ws"]
         model.last_loss = out["loss"]
         return out["loss"][0].clone()
 
     @staticmethod
     def backward(ctx, gout):
+        (params,) = ctx.saved_tensors
+        _load_params(ctx.model, params)
         g = gout.detach().reshape(1).to(torch.float32).contiguous()
         res = ctx.model.backward(ctx.x, ctx.ws, gloss=g)
         ctx.ws = None

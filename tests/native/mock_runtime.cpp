@@ -22,9 +22,12 @@ std::atomic<long long> g_delay_us{200};
 using Clock = std::chrono::steady_clock;
 struct MockEvent { Clock::time_point ready; };
 std::unordered_map<void*, MockEvent*> g_events;
+std::atomic<int> g_fail_encodes{0};
 }  // namespace
 
 extern "C" void mock_set_delay_us(long long us) { g_delay_us = us; }
+// The next n tok_encode calls fail with TOK_EDEVICE (a launch that fails).
+extern "C" void mock_fail_next_encodes(int n) { g_fail_encodes = n; }
 
 hipError_t hipMalloc(void** p, size_t n) { *p = std::malloc(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
 hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
@@ -64,6 +67,10 @@ tok_status tok_workspace_size(const tok_model*, int N, int T, int H, int W, int 
 }
 tok_status tok_encode(tok_model*, const uint8_t* x, int N, int T, int H, int W, float* z, float* codes,
                       int32_t* idx, const tok_drop_desc*, uint8_t* keep, void*, size_t, hipStream_t) {
+  if (g_fail_encodes.load() > 0) {
+    --g_fail_encodes;
+    return TOK_EDEVICE;
+  }
   const size_t tok = (size_t)((T - 1) / 4 + 1) * (H / 4) * (W / 4);
   const size_t pix = (size_t)T * H * W * 3;
   for (int n = 0; n < N; ++n) {

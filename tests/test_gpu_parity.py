@@ -149,9 +149,10 @@ def test_bf16_roundtrip_psnr(tk, models):
     p_gpu = O.psnr(xh.cpu().numpy(), src)
     p_ref = O.psnr(ref["xhat"], src)
     assert abs(p_gpu - p_ref) <= 0.5, (p_gpu, p_ref)
-    # decode of the oracle's codes: PSNR of the bf16 reconstruction against the oracle's
+    # decode of the oracle's codes: PSNR of the bf16 reconstruction against the
+    # oracle's, floor derived from bf16's precision (tests/test_gpu_fullframe.py)
     p_dec = O.psnr(xd.cpu().numpy(), ref["xhat"])
-    assert p_dec > 25.0, p_dec
+    assert p_dec >= 32.0, p_dec
     _, agree, _ = G.idx_agreement(out["idx"].cpu().numpy(), ref["idx"], ref["b"])
     assert agree > 0.9, agree
 

@@ -35,6 +35,7 @@ def lib():
                                     C.POINTER(sz)]
     lb.tok_server_destroy.argtypes = [vp]
     lb.mock_set_delay_us.argtypes = [C.c_longlong]
+    lb.mock_fail_next_encodes.argtypes = [C.c_int]
     return lb
 
 
@@ -156,4 +157,31 @@ def test_budget_bounds_concurrency(lib):
         lib.tok_server_release(sv.h, t)
         one = max(one, sv.stats()["peak"])
     assert one <= 1 << 30
+    sv.close()
+
+
+def test_failed_launch_leaves_no_view_of_its_block(lib):
+    """A batch whose launch fails returns its result block to the arena; the
+    failed request must not keep a view of it: the next batch reuses the same
+    block, and neither waiting on nor releasing the failed request may shift
+    the next clip's views or free its block."""
+    sv = Server(lib, 1 << 30, slots=1, max_batch=1, delay_us=20000)
+    lib.mock_fail_next_encodes(1)
+    rc, ta = sv.submit(7, 5, 32, 32)
+    assert rc == 0
+    rc, ra = sv.wait(ta)
+    assert rc == 0 and ra.status == -4  # TOK_EDEVICE
+    rc, tb = sv.submit(9, 5, 32, 32)
+    assert rc == 0
+    rc, rb = sv.wait(tb)
+    assert rc == 0 and rb.status == 0 and rb.batch_size == 1
+    assert C.cast(rb.codes, C.POINTER(C.c_float))[0] == 9.0
+    assert lib.tok_server_release(sv.h, ta) == 0
+    in_use = sv.stats()["in_use"]
+    assert in_use > 0  # the second clip's block is still held
+    rc, rb2 = sv.wait(tb)
+    assert rc == 0 and rb2.codes == rb.codes
+    assert C.cast(rb2.codes, C.POINTER(C.c_float))[0] == 9.0
+    assert lib.tok_server_release(sv.h, tb) == 0
+    assert sv.stats()["in_use"] == 0
     sv.close()
