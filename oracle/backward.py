@@ -113,6 +113,16 @@ def group_norm_backward(x, gamma, gy, groups=GN_GROUPS, eps=GN_EPS):
     return dx, dgamma, dbeta
 
 
+def fsq_ste_backward(z, g_zt):
+    """Gradient with respect to z of the quantiser under the straight-through
+    rule: c = rint(b) / floor(L/2) passes dL/dc unchanged to
+    z~ = b / floor(L/2), and b = tanh(z + s) h - o, so
+    dL/dz = dL/dz~ * (h / floor(L/2)) * (1 - tanh^2(z + s))."""
+    h, o, s, dd = fsq_constants()
+    th = np.tanh(np.asarray(z, np.float64) + s)
+    return g_zt * (h / dd) * (1.0 - th * th)
+
+
 def silu_backward(a, g):
     s = sigmoid(a)
     return g * s * (1.0 + a * (1.0 - s))
@@ -211,10 +221,30 @@ def train_backward(tape, p, gx_hat=None):
     caller can evaluate the gradient for another valid choice at such pixels;
     everything after the seed is the same adjoint.
     """
-    grads = {}
     x, xhat = tape["x"], tape["xhat"]
     if gx_hat is None:
         gx_hat = np.sign(xhat - x) / xhat.size
+    zt, codes = tape["zt"], tape["codes"]
+    g_commit = 2.0 * COMMIT_WEIGHT * (zt - codes) / zt.size
+    return _adjoint(tape, p, gx_hat, g_zt_extra=g_commit)
+
+
+def outputs_backward(tape, p, g_xhat, g_codes=None, g_z=None):
+    """Adjoint of the codec's outputs for gradients that come from outside
+    (a loss computed by the caller; the gradient interface of Sec. 4.1):
+    returns (grads dict, dx) of the scalar
+        <g_xhat, x_hat> + <g_codes, keep * c> + <g_z, z>
+    where keep * c is the zero-filled code tensor the decoder reads (Eq. 7),
+    z the pre-quantisation latent, and the straight-through rule dc/dz~ = 1
+    applies.  No loss term of train_forward's own enters."""
+    return _adjoint(tape, p, g_xhat, g_dec_extra=g_codes, g_z_extra=g_z)
+
+
+def _adjoint(tape, p, gx_hat, g_dec_extra=None, g_zt_extra=None, g_z_extra=None):
+    """Back-propagation from dL/dx_hat through decoder, quantiser and encoder.
+    g_dec_extra is added to the gradient of the decoder input keep * c,
+    g_zt_extra to that of z~, g_z_extra to that of z."""
+    grads = {}
     gw, gb = conv3d_wgrad(tape["r2"], gx_hat, p["dec.conv_out.w"].shape)
     grads["dec.conv_out.w"], grads["dec.conv_out.b"] = gw, gb
     g = conv3d_dgrad(gx_hat, p["dec.conv_out.w"], tape["r2"].shape)
@@ -229,12 +259,15 @@ def train_backward(tape, p, gx_hat=None):
     gw, gb = conv3d_wgrad(tape["dec_in"], g, p["dec.proj_in.w"].shape)
     grads["dec.proj_in.w"], grads["dec.proj_in.b"] = gw, gb
     g_dec_in = conv3d_dgrad(g, p["dec.proj_in.w"], tape["dec_in"].shape)
+    if g_dec_extra is not None:
+        g_dec_in = g_dec_in + g_dec_extra
     # straight-through: d(codes)/d(z~) = 1; the mask multiplies the decoder path
-    zt, codes = tape["zt"], tape["codes"]
-    g_zt = g_dec_in * tape["keep"] + 2.0 * COMMIT_WEIGHT * (zt - codes) / zt.size
-    h, o, s, dd = fsq_constants()
-    th = np.tanh(tape["z"] + s)
-    g_z = g_zt * (h / dd) * (1.0 - th * th)
+    g_zt = g_dec_in * tape["keep"]
+    if g_zt_extra is not None:
+        g_zt = g_zt + g_zt_extra
+    g_z = fsq_ste_backward(tape["z"], g_zt)
+    if g_z_extra is not None:
+        g_z = g_z + g_z_extra
     gw, gb = conv3d_wgrad(tape["d2"], g_z, p["enc.proj.w"].shape)
     grads["enc.proj.w"], grads["enc.proj.b"] = gw, gb
     g = conv3d_dgrad(g_z, p["enc.proj.w"], tape["d2"].shape)

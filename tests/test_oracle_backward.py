@@ -187,3 +187,46 @@ def test_gradient_finite_difference_config0_clip():
         an = sum(float(np.vdot(grads[k], d[k])) for k in d)
         assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
     assert dx.shape == (1, 9, 64, 64, 3)
+
+
+def test_outputs_backward_finite_difference(tiny):
+    """The adjoint for gradients from outside (the codec's gradient interface):
+    F = <g_xhat, x_hat> + <g_codes, keep c> + <g_z, z> on the frozen-rounding
+    surrogate, one random direction per parameter tensor and the input, rel 1e-6;
+    with g_codes = g_z = 0 it is train_backward's adjoint from the same seed."""
+    u8, p, keep = tiny
+    _, tape = B.train_forward(u8, p, keep)
+    rng = np.random.default_rng(21)
+    gx = rng.standard_normal(tape["xhat"].shape)
+    gc = rng.standard_normal(tape["dec_in"].shape)
+    gz = rng.standard_normal(tape["z"].shape)
+    grads, dx = B.outputs_backward(tape, p, gx, gc, gz)
+    frozen = _frozen(tape)
+
+    def F(pp, u=None):
+        _, t = B.train_forward(u8 if u is None else u, pp, keep, frozen)
+        return float(np.vdot(gx, t["xhat"]) + np.vdot(gc, t["dec_in"]) + np.vdot(gz, t["z"]))
+
+    h = 1e-6
+    for name, _, shape in synth.param_spec():
+        v = rng.standard_normal(shape)
+        v /= np.linalg.norm(v)
+        fd = (F({**p, name: p[name] + h * v}) - F({**p, name: p[name] - h * v})) / (2 * h)
+        an = float(np.vdot(grads[name], v))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-4 * np.linalg.norm(grads[name]), 1e-9), (name, fd, an)
+    # the zero-seed special case reduces to the loss adjoint's structure
+    g0, dx0 = B.outputs_backward(tape, p, gx)
+    g1, dx1 = B._adjoint(tape, p, gx)
+    for k in g0:
+        np.testing.assert_array_equal(g0[k], g1[k])
+    np.testing.assert_array_equal(dx0, dx1)
+
+
+def test_fsq_ste_backward_finite_difference():
+    """dz~/dz by central differences of b / floor(L/2) away from saturation."""
+    z = np.linspace(-2.0, 2.0, 61)[:, None] * np.ones((1, 6))
+    dd = O.fsq_constants()[3]
+    zt = lambda v: O.fsq(v)[3] / dd  # noqa: E731  (b of the quantiser's forward, normalised)
+    eps = 1e-6
+    fd = (zt(z + eps) - zt(z - eps)) / (2 * eps)
+    np.testing.assert_allclose(B.fsq_ste_backward(z, np.ones_like(z)), fd, rtol=1e-8, atol=1e-12)
