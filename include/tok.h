@@ -336,6 +336,117 @@ tok_status tok_conv3d_wgrad(tok_precision prec, int view, const void* x, int N, 
                             const void* dy, int To, int Ho, int Wo, int Cout, float* dw, float* db, void* ws,
                             size_t ws_bytes, hipStream_t stream);
 
+/* Backward pass of the last tok_train_forward (same x, shape and ws) for
+ * gradients of its outputs that come from the caller, e.g. a loss computed
+ * outside the library: the codec is one differentiable stage of a larger
+ * model (Sec. 4.1, the codec's internal gradient interface; Appendix Eq. 7,
+ * gradients through the zero-filled decoder input).  Writes the gradient of
+ *   <gxhat, x_hat> + <gcodes, keep * c> + <gz, z>
+ * with respect to every parameter (dweights, canonical blob order, every
+ * entry written) and, if dx is not NULL, to the normalised input
+ * x/127.5 - 1 (float32 (N,T,H,W,3)).  x_hat is the reconstruction, keep * c
+ * the zero-filled FSQ codes the decoder read (tok_train_codes), z the
+ * pre-quantisation latent; the straight-through rule dc/dz~ = 1 applies and
+ * dropped tokens pass no gradient from the decoder or from gcodes.  The
+ * library's own loss terms do not enter.  gxhat: device float32 (N,T,H,W,3),
+ * required; gcodes, gz: device float32 (N,T2,H2,W2,6) or NULL (zero).
+ * Errors as tok_backward. */
+tok_status tok_backward_outputs(tok_model* model, const uint8_t* x, int N, int T, int H, int W,
+                                const float* gxhat, const float* gcodes, const float* gz,
+                                float* dweights, float* dx, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* Copy the zero-filled codes keep * c (N,T2,H2,W2,6 float32) that the last
+ * tok_train_forward on ws fed to the decoder. */
+tok_status tok_train_codes(tok_model* model, int N, int T, int H, int W, float* codes,
+                           const void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Per-operation entry points: the building blocks of the codec, each with its
+ * adjoint, for torch.autograd.Function wrappers and for models that use the
+ * codec's layers outside the fixed encode / decode graphs.  They run the same
+ * kernels as tok_encode / tok_decode / tok_backward.
+ *
+ * prec is TOK_F32 or TOK_BF16 (TOK_EUNSUPPORTED otherwise).  Activations use
+ * the library's chunked layout [N][T][ceil(C/CH)][H][W][CH] of prec, CH = 64
+ * bytes / element size (16 fp32, 32 bf16), channels past C zero, 16-byte
+ * aligned; tok_op_act_pack / tok_op_act_unpack convert from and to dense
+ * channels-last float32.  Workspaces are device memory, 256-byte aligned, of
+ * the size the matching *_workspace_size call returns; their contents are not
+ * preserved.  Every call is asynchronous on `stream`; nothing allocates.
+ * -------------------------------------------------------------------------*/
+
+/* dense float32 [frames][HW][C] -> chunked activations of prec, and back
+ * (frames = N T, HW = H W; channels past C are written as zero / dropped). */
+tok_status tok_op_act_pack(tok_precision prec, const float* src, int frames, int HW, int C, void* dst,
+                           hipStream_t stream);
+tok_status tok_op_act_unpack(tok_precision prec, const void* src, int frames, int HW, int C,
+                             float* dst, hipStream_t stream);
+
+/* Causal 3x3x3 convolution (the encoder's and decoder's conv layers):
+ *   y[n,t,h,w,o] = b[o] + sum over kt,kh,kw,i of w[o][i][kt][kh][kw] x~[n, s t + kt - 2,
+ *                  s h + kh - 1, s w + kw - 1, i]   (+ resid[n,t,h,w,o])
+ * with frame indices below 0 reading frame 0 (causal replicate padding) and
+ * spatial indices outside the frame reading 0.  view 0: stride s = 1
+ * (To,Ho,Wo = Ti,Hi,Wi); view 1: stride 2 in t, h, w (Ti odd, Hi and Wi even;
+ * To = (Ti-1)/2+1, Ho = Hi/2, Wo = Wi/2: output frame 0 sees input frame 0
+ * only); view 2: the input upsampled first by nearest x2 in h, w with time
+ * map t -> ceil(t/2) (To = 2 Ti - 1, Ho = 2 Hi, Wo = 2 Wi), then stride 1.
+ * w: device float32 [Cout][Cin][3][3][3]; b: device float32 [Cout] or NULL.
+ * Channels: Cin and Cout multiples of 64 (chunked activations), or the first
+ * layer Cin = 3 -> Cout = 64 at view 0, whose x is uint8 pixels (N,Ti,Hi,Wi,3)
+ * normalised as x/127.5 - 1, or the last layer Cout = 3 at view 0, whose y
+ * (and dy) is dense float32 (N,To,Ho,Wo,3).  resid: optional chunked tensor of
+ * y's shape added to the output (view 0, Cout multiple of 64; it may alias y).
+ * dgrad writes dx = J^T dy (dx of Cin = 3 is dense float32 (N,Ti,Hi,Wi,3), the
+ * gradient for the normalised pixels); wgrad writes dw = dL/dw (same layout as
+ * w, float32) and, if db is not NULL, db = dL/db, both deterministic.  Errors:
+ * TOK_EINVAL (null / misaligned pointer, view outside 0..2), TOK_ESHAPE (shape
+ * does not fit the view, N T above 65535), TOK_EUNSUPPORTED (channels or
+ * precision), TOK_EWORKSPACE. */
+tok_status tok_op_conv3d_workspace_size(tok_precision prec, int view, int N, int Ti, int Hi, int Wi,
+                                        int Cin, int Cout, size_t* bytes);
+tok_status tok_op_conv3d_fwd(tok_precision prec, int view, const void* x, int N, int Ti, int Hi,
+                             int Wi, int Cin, const float* w, const float* b, const void* resid,
+                             void* y, int Cout, void* ws, size_t ws_bytes, hipStream_t stream);
+tok_status tok_op_conv3d_dgrad(tok_precision prec, int view, const void* dy, int N, int Ti, int Hi,
+                               int Wi, int Cin, const float* w, void* dx, int Cout, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+tok_status tok_op_conv3d_wgrad(tok_precision prec, int view, const void* x, int N, int Ti, int Hi,
+                               int Wi, int Cin, const void* dy, int Cout, float* dw, float* db,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* GroupNorm(32) with SiLU, per frame (the residual blocks' normalisation):
+ * 64 channels in 32 groups of 2; the statistics of frame f and group g are
+ * the mean and biased variance over the HW positions and the group's 2
+ * channels.  x: chunked (frames = N T, HW = H W, 64 channels).
+ * gn_stats: mean_rstd float32 [frames][32][2] = (mean, 1/sqrt(var + eps)).
+ * gn_apply: y = SiLU((x - mean) rstd gamma[c] + beta[c]) (y may equal x).
+ * gn_bwd:   dx = J^T dy of gn_apply at x (plus resid if not NULL; dx may
+ *           alias dy or resid), dgamma[64] and dbeta[64] (written, not
+ *           accumulated), deterministic.
+ * gamma, beta: device float32 [64].  Errors: TOK_EINVAL, TOK_ESHAPE (frames
+ * above 16383 (bf16: 32767) or empty), TOK_EUNSUPPORTED, TOK_EWORKSPACE. */
+tok_status tok_op_gn_workspace_size(tok_precision prec, int frames, int HW, size_t* bytes);
+tok_status tok_op_gn_stats(tok_precision prec, const void* x, int frames, int HW, float eps,
+                           float* mean_rstd, void* ws, size_t ws_bytes, hipStream_t stream);
+tok_status tok_op_gn_apply(tok_precision prec, const void* x, int frames, int HW,
+                           const float* mean_rstd, const float* gamma, const float* beta, void* y,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+tok_status tok_op_gn_bwd(tok_precision prec, const void* x, const void* dy, int frames, int HW,
+                         const float* mean_rstd, const float* gamma, const float* beta,
+                         const void* resid, void* dx, float* dgamma, float* dbeta, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* Straight-through adjoint of FSQ (tok_quantize) on n_tokens latent vectors:
+ *   gz = gz_in + keep * gcodes * (h / floor(L/2)) * (1 - tanh^2(z + s))
+ * per channel (the rounding passes the gradient of the codes unchanged to
+ * the unrounded b / floor(L/2), b = tanh(z + s) h - o).  z, gcodes, gz_in,
+ * gz: device float32 (n_tokens, 6); keep: device uint8 (n_tokens) or NULL
+ * (all kept); gcodes or gz_in may be NULL (zero).  gz may alias gz_in. */
+tok_status tok_op_fsq_ste_bwd(const float* z, const uint8_t* keep, const float* gcodes,
+                              const float* gz_in, size_t n_tokens, float* gz, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Streaming request loop (continuous batching under an HBM budget).
  *

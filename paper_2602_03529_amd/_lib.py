@@ -99,6 +99,32 @@ def lib():
     L.tok_conv3d_wgrad_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, i32, C.POINTER(sz)]
     L.tok_conv3d_wgrad.restype = i32
     L.tok_conv3d_wgrad.argtypes = [i32, i32, vp, i32, i32, i32, i32, i32, vp, i32, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.tok_backward_outputs.restype = i32
+    L.tok_backward_outputs.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.tok_train_codes.restype = i32
+    L.tok_train_codes.argtypes = [vp, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.tok_op_act_pack.restype = i32
+    L.tok_op_act_pack.argtypes = [i32, vp, i32, i32, i32, vp, vp]
+    L.tok_op_act_unpack.restype = i32
+    L.tok_op_act_unpack.argtypes = [i32, vp, i32, i32, i32, vp, vp]
+    L.tok_op_conv3d_workspace_size.restype = i32
+    L.tok_op_conv3d_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_op_conv3d_fwd.restype = i32
+    L.tok_op_conv3d_fwd.argtypes = [i32, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, i32, vp, sz, vp]
+    L.tok_op_conv3d_dgrad.restype = i32
+    L.tok_op_conv3d_dgrad.argtypes = [i32, i32, vp, i32, i32, i32, i32, i32, vp, vp, i32, vp, sz, vp]
+    L.tok_op_conv3d_wgrad.restype = i32
+    L.tok_op_conv3d_wgrad.argtypes = [i32, i32, vp, i32, i32, i32, i32, i32, vp, i32, vp, vp, vp, sz, vp]
+    L.tok_op_gn_workspace_size.restype = i32
+    L.tok_op_gn_workspace_size.argtypes = [i32, i32, i32, C.POINTER(sz)]
+    L.tok_op_gn_stats.restype = i32
+    L.tok_op_gn_stats.argtypes = [i32, vp, i32, i32, C.c_float, vp, vp, sz, vp]
+    L.tok_op_gn_apply.restype = i32
+    L.tok_op_gn_apply.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+    L.tok_op_gn_bwd.restype = i32
+    L.tok_op_gn_bwd.argtypes = [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.tok_op_fsq_ste_bwd.restype = i32
+    L.tok_op_fsq_ste_bwd.argtypes = [vp, vp, vp, vp, sz, vp, vp]
     L.tok_profile_begin.restype = i32
     L.tok_profile_begin.argtypes = [vp]
     L.tok_profile_end.restype = i32

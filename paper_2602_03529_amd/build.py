@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtok.so")
 SOURCES = ["conv3d.hip", "pointwise.hip", "backward.hip", "tok_api.hip", "tok_train.hip", "tok_serve.hip", "tokens.hip",
-           "packets.hip", "enhance.hip", "tok_coding.hip"]
+           "packets.hip", "enhance.hip", "tok_coding.hip", "ops.hip", "tok_ops.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

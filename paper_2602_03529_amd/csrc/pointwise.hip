@@ -57,6 +57,7 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float4* __restri
     const float var = q / n;
     const float rstd = 1.0f / sqrtf(var + eps);
     if (mr && j == 0) mr[(size_t)frame * 32 + g] = make_float2(m, rstd);
+    if (!gamma) return;  // statistics only
     const float sc = rstd * gamma[c];
     scale[(size_t)frame * 64 + c] = sc;
     shift[(size_t)frame * 64 + c] = beta[c] - m * sc;

@@ -130,7 +130,8 @@ hipError_t launch_pack_weights(const float* w, int Cout, int Cin, int prec, int 
 
 // GroupNorm: merge per-tile partials of each (n, t) frame into per-channel
 // scale/shift for the consumer's prologue.
-// With mr set, also the (mean, rstd) of each (frame, group) for the backward.
+// With mr set, also the (mean, rstd) of each (frame, group) for the backward;
+// with gamma null only mr is written (scale, shift, beta unused).
 hipError_t launch_gn_finalize(const float4* stats, int frames, int tiles, const float* gamma,
                               const float* beta, float eps, float* scale, float* shift, float2* mr,
                               hipStream_t s);
@@ -239,5 +240,27 @@ hipError_t launch_proj6(const void* x, size_t ntok, int HW, const float* w6, flo
 hipError_t launch_outer6(const float* a6, const void* x, size_t ntok, int HW, int prec, float* partial,
                          int transposed, float* dw, float* db, hipStream_t s);
 hipError_t launch_transpose(const float* in, int R, int C, float* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Per-operation entry points (ops.hip).
+// ---------------------------------------------------------------------------
+// dense [frames][HW][C] float <-> chunked activations of prec (channels past C
+// zero when packing, dropped when unpacking).
+hipError_t launch_act_pack(const float* src, long long frames, int HW, int C, int prec, void* dst, hipStream_t s);
+hipError_t launch_act_unpack(const void* src, long long frames, int HW, int C, int prec, float* dst, hipStream_t s);
+// GroupNorm(32) per-tile partials of a 64-channel chunked tensor (the layout
+// launch_gn_finalize merges), gn_op_tiles(HW) tiles per frame.
+int gn_op_tiles(int HW);
+hipError_t launch_gn_partials(const void* x, int frames, int HW, int prec, float4* stats, hipStream_t s);
+// scale / shift [frames][64] from (mean, rstd) [frames][32] and the affine.
+hipError_t launch_gn_affine(const float2* mr, const float* gamma, const float* beta, int frames, float* scale,
+                            float* shift, hipStream_t s);
+// g_z = g_z_in + keep (g_a + g_b) dz~/dz (straight-through quantiser); any
+// input may be null.
+hipError_t launch_fsq_ste(const float* z, const uint8_t* keep, const float* ga, const float* gb, const float* gzin,
+                          size_t ntok, const FsqConst& fc, float* gz, hipStream_t s);
+// dense float (npos, 3) -> one-chunk activations (channels 3.. zero).
+hipError_t launch_rgb_to_chunk(const float* src, size_t npos, int prec, void* out, hipStream_t s);
+hipError_t launch_fill_zero(float* p, size_t n, hipStream_t s);
 
 }  // namespace tok

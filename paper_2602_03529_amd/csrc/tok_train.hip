@@ -338,8 +338,22 @@ tok_status tok_train_forward(tok_model* m, const uint8_t* x, int N, int T, int H
   return TOK_OK;
 }
 
-tok_status tok_backward(tok_model* m, const uint8_t* x, int N, int T, int H, int W, const float* gloss,
-                        float* dweights, float* dx, void* ws, size_t ws_bytes, hipStream_t s) {
+}  // extern "C"
+
+namespace {
+
+// Where the backward pass starts: the library's own objective (scaled by
+// gloss), or gradients of the forward's outputs that come from the caller.
+struct Seeds {
+  bool own_loss;
+  const float* gloss;   // own loss: device scalar or null (1)
+  const float* gxhat;   // caller: dL/dx_hat (N,T,H,W,3)
+  const float* gcodes;  // caller: dL/d(keep * c) (N,T2,H2,W2,6) or null
+  const float* gz;      // caller: dL/dz (N,T2,H2,W2,6) or null
+};
+
+tok_status backward_impl(tok_model* m, const uint8_t* x, int N, int T, int H, int W, const Seeds& sd,
+                         float* dweights, float* dx, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!m || !x || !dweights || !ws) return fail(TOK_EINVAL, "null argument");
   TrainPlan p;
   tok_status st;
@@ -353,7 +367,10 @@ tok_status tok_backward(tok_model* m, const uint8_t* x, int N, int T, int H, int
   // seed: dL/dx_hat
   {
     Timed tm(m, K_BWD_MISC, s);
-    TOK_HIP(launch_l1(c.at<float>(p.XHAT), x, p.npos, m->prec, gloss, c.at(p.GX), c.at<float>(p.L1P), s));
+    if (sd.own_loss)
+      TOK_HIP(launch_l1(c.at<float>(p.XHAT), x, p.npos, m->prec, sd.gloss, c.at(p.GX), c.at<float>(p.L1P), s));
+    else
+      TOK_HIP(launch_rgb_to_chunk(sd.gxhat, p.npos, m->prec, c.at(p.GX), s));
   }
   // conv_out, decoder residual blocks
   TOK_TRY(wgrad(c, L_CONV_OUT, CM_S1, c.at(p.R2), T, H, W, c.at(p.GX), T, H, W, dweights));
@@ -378,9 +395,13 @@ tok_status tok_backward(tok_model* m, const uint8_t* x, int N, int T, int H, int
     TOK_HIP(launch_outer6(c.at<float>(p.DEC), c.at(p.G2a), p.ntok, HW2, m->prec, c.at<float>(p.O6P), 1,
                           dweights + m->w_off[L_PROJ_IN], dweights + m->b_off[L_PROJ_IN], s));
     TOK_HIP(launch_proj6(c.at(p.G2a), p.ntok, HW2, m->w1x1T[L_PROJ_IN], c.at<float>(p.GDEC), m->prec, s));
-    TOK_HIP(launch_fsq_bwd(c.at<float>(p.Z), c.at<uint8_t>(p.KEEP), c.at<float>(p.GDEC), p.ntok, fc,
-                           2.0f * kCommitWeight / (float)(p.ntok * 6), gloss, c.at<float>(p.GZ), c.at<float>(p.CMP),
-                           s));
+    if (sd.own_loss)
+      TOK_HIP(launch_fsq_bwd(c.at<float>(p.Z), c.at<uint8_t>(p.KEEP), c.at<float>(p.GDEC), p.ntok, fc,
+                             2.0f * kCommitWeight / (float)(p.ntok * 6), sd.gloss, c.at<float>(p.GZ),
+                             c.at<float>(p.CMP), s));
+    else
+      TOK_HIP(launch_fsq_ste(c.at<float>(p.Z), c.at<uint8_t>(p.KEEP), c.at<float>(p.GDEC), sd.gcodes, sd.gz, p.ntok,
+                             fc, c.at<float>(p.GZ), s));
     TOK_HIP(launch_outer6(c.at<float>(p.GZ), c.at(p.D2), p.ntok, HW2, m->prec, c.at<float>(p.O6P), 0,
                           dweights + m->w_off[L_PROJ], dweights + m->b_off[L_PROJ], s));
     TOK_HIP(launch_proj_in(c.at<float>(p.GZ), N, d.T2, 0, d.T2, HW2, m->w1x1T[L_PROJ], m->zeros, m->prec,
@@ -409,6 +430,34 @@ tok_status tok_backward(tok_model* m, const uint8_t* x, int N, int T, int H, int
   }
   TOK_TRY(wgrad(c, L_CONV_IN, CM_S1, c.at(p.GX), T, H, W, GB, T, H, W, dweights));
   if (dx) TOK_TRY(adj(c, L_CONV_IN, GB, T, H, W, dx, OUT_RGB32));
+  return TOK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tok_status tok_backward(tok_model* m, const uint8_t* x, int N, int T, int H, int W, const float* gloss,
+                        float* dweights, float* dx, void* ws, size_t ws_bytes, hipStream_t s) {
+  const Seeds sd{true, gloss, nullptr, nullptr, nullptr};
+  return backward_impl(m, x, N, T, H, W, sd, dweights, dx, ws, ws_bytes, s);
+}
+
+tok_status tok_backward_outputs(tok_model* m, const uint8_t* x, int N, int T, int H, int W, const float* gxhat,
+                                const float* gcodes, const float* gz, float* dweights, float* dx, void* ws,
+                                size_t ws_bytes, hipStream_t s) {
+  if (!gxhat) return fail(TOK_EINVAL, "null gxhat");
+  const Seeds sd{false, nullptr, gxhat, gcodes, gz};
+  return backward_impl(m, x, N, T, H, W, sd, dweights, dx, ws, ws_bytes, s);
+}
+
+tok_status tok_train_codes(tok_model* m, int N, int T, int H, int W, float* codes, const void* ws, size_t ws_bytes,
+                           hipStream_t s) {
+  if (!m || !codes || !ws) return fail(TOK_EINVAL, "null argument");
+  TrainPlan p;
+  tok_status st;
+  if (!check_ws(m, N, T, H, W, ws_bytes, &p, &st)) return st;
+  TOK_HIP(hipMemcpyAsync(codes, static_cast<const char*>(ws) + p.DEC, p.ntok * 6 * 4, hipMemcpyDeviceToDevice, s));
   return TOK_OK;
 }
 

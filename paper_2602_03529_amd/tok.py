@@ -187,6 +187,37 @@ class TokModel:
         return dict(dweights=dweights, dx=dxt)
 
 
+    def backward_outputs(self, x: torch.Tensor, ws: torch.Tensor, gxhat: torch.Tensor,
+                         gcodes: torch.Tensor | None = None, gz: torch.Tensor | None = None,
+                         dweights: torch.Tensor | None = None, dx=False):
+        """Gradients of <gxhat, x_hat> + <gcodes, keep c> + <gz, z> for the last
+        train_forward on (x, ws) (tok_backward_outputs): dict(dweights, dx)."""
+        N, T, H, W, _ = x.shape
+        _need(x, torch.uint8, (N, T, H, W, 3), "x")
+        T2, H2, W2 = latent_shape(T, H, W)
+        dev = x.device
+        _need(gxhat, torch.float32, (N, T, H, W, 3), "gxhat")
+        for t, nm in ((gcodes, "gcodes"), (gz, "gz")):
+            if t is not None:
+                _need(t, torch.float32, (N, T2, H2, W2, 6), nm)
+        if dweights is None:
+            dweights = torch.empty(weight_count(), dtype=torch.float32, device=dev)
+        dxt = torch.empty((N, T, H, W, 3), dtype=torch.float32, device=dev) if dx else None
+        L.check("tok_backward_outputs", self.lib.tok_backward_outputs(
+            self.handle, _ptr(x), N, T, H, W, _ptr(gxhat), _ptr(gcodes), _ptr(gz), _ptr(dweights), _ptr(dxt),
+            _ptr(ws), ws.numel(), _stream(dev)))
+        return dict(dweights=dweights, dx=dxt)
+
+    def train_codes(self, x_shape, ws: torch.Tensor) -> torch.Tensor:
+        """The zero-filled codes keep * c the last train_forward on ws decoded."""
+        N, T, H, W = x_shape[:4]
+        T2, H2, W2 = latent_shape(T, H, W)
+        codes = torch.empty((N, T2, H2, W2, 6), dtype=torch.float32, device=ws.device)
+        L.check("tok_train_codes", self.lib.tok_train_codes(self.handle, N, T, H, W, _ptr(codes), _ptr(ws),
+                                                            ws.numel(), _stream(ws.device)))
+        return codes
+
+
 def conv3d_wgrad(x: torch.Tensor, dy: torch.Tensor, shape_x, shape_y, Cin: int, Cout: int, view: int,
                  precision: str = "bf16", with_bias: bool = True):
     """tok_conv3d_wgrad on chunked-layout device tensors x, dy (float32 or
@@ -248,6 +279,263 @@ class TokenizerLoss(torch.autograd.Function):
 def tokenizer_loss(model: "TokModel", params: torch.Tensor, x: torch.Tensor, keep: torch.Tensor | None = None):
     """Differentiable training loss; params: float32 (weight_count(),) cuda tensor."""
     return TokenizerLoss.apply(params, model, x, keep)
+
+
+class Tokenizer(torch.autograd.Function):
+    """The codec as one differentiable stage (Sec. 4.1 gradient interface):
+    forward returns (x_hat, keep * c, z) of tok_train_forward for `params`;
+    backward takes the gradients of those three outputs from whatever loss the
+    caller computes and runs tok_backward_outputs (straight-through
+    quantiser), returning the parameter gradient.  The tape lives in the
+    call's own workspace until its backward has run."""
+
+    @staticmethod
+    def forward(ctx, params, model, x, keep):
+        _load_params(model, params)
+        out = model.train_forward(x, keep, xhat=True, z=True)
+        codes = model.train_codes(tuple(x.shape), out["ws"])
+        ctx.save_for_backward(params)
+        ctx.model, ctx.x, ctx.ws = model, x, out["ws"]
+        return out["xhat"], codes, out["z"]
+
+    @staticmethod
+    def backward(ctx, gxhat, gcodes, gz):
+        (params,) = ctx.saved_tensors
+        _load_params(ctx.model, params)
+        x = ctx.x
+        N, T, H, W, _ = x.shape
+        if gxhat is None:
+            gxhat = torch.zeros((N, T, H, W, 3), dtype=torch.float32, device=x.device)
+        prep = (lambda g: None if g is None else g.detach().to(torch.float32).contiguous())
+        res = ctx.model.backward_outputs(x, ctx.ws, prep(gxhat), prep(gcodes), prep(gz))
+        ctx.ws = None
+        return res["dweights"], None, None, None
+
+
+def tokenizer(model: "TokModel", params: torch.Tensor, x: torch.Tensor, keep: torch.Tensor | None = None):
+    """(x_hat, zero-filled codes, z) as differentiable functions of params."""
+    return Tokenizer.apply(params, model, x, keep)
+
+
+# ---------------------------------------------------------------------------
+# Per-operation entry points (tok_op_*) and their autograd wrappers.
+# Activations are torch tensors in the library's chunked layout
+# (N, T, ceil(C/CH), H, W, CH) of float32 (CH = 16) or bfloat16 (CH = 32).
+# ---------------------------------------------------------------------------
+_OP_DTYPES = {"f32": torch.float32, "bf16": torch.bfloat16}
+
+
+def _prec_of(t: torch.Tensor) -> str:
+    for k, v in _OP_DTYPES.items():
+        if t.dtype == v:
+            return k
+    raise ValueError("activations are float32 or bfloat16, got %s" % t.dtype)
+
+
+def act_shape(N, T, H, W, C, precision):
+    ch = 32 if precision == "bf16" else 16
+    return (N, T, (C + ch - 1) // ch, H, W, ch)
+
+
+def act_pack(x: torch.Tensor, precision: str = "bf16") -> torch.Tensor:
+    """Dense float32 (N, T, H, W, C) -> chunked activations (tok_op_act_pack)."""
+    assert x.dtype == torch.float32 and x.dim() == 5 and x.is_cuda and x.is_contiguous()
+    N, T, H, W, Cc = x.shape
+    out = torch.empty(act_shape(N, T, H, W, Cc, precision), dtype=_OP_DTYPES[precision], device=x.device)
+    L.check("tok_op_act_pack", L.lib().tok_op_act_pack(PRECISIONS[precision], _ptr(x), N * T, H * W, Cc,
+                                                       _ptr(out), _stream(x.device)))
+    return out
+
+
+def act_unpack(a: torch.Tensor, C_: int) -> torch.Tensor:
+    """Chunked activations (N, T, chunks, H, W, CH) -> dense float32 (N, T, H, W, C)."""
+    assert a.dim() == 6 and a.is_cuda and a.is_contiguous()
+    N, T, _, H, W, _ = a.shape
+    out = torch.empty((N, T, H, W, C_), dtype=torch.float32, device=a.device)
+    L.check("tok_op_act_unpack", L.lib().tok_op_act_unpack(PRECISIONS[_prec_of(a)], _ptr(a), N * T, H * W, C_,
+                                                           _ptr(out), _stream(a.device)))
+    return out
+
+
+def _view_out(view, Ti, Hi, Wi):
+    if view == 0:
+        return Ti, Hi, Wi
+    if view == 1:
+        return (Ti - 1) // 2 + 1, Hi // 2, Wi // 2
+    return 2 * Ti - 1, 2 * Hi, 2 * Wi
+
+
+def _conv_ws(precision, view, N, Ti, Hi, Wi, Cin, Cout, dev):
+    n = C.c_size_t()
+    L.check("tok_op_conv3d_workspace_size", L.lib().tok_op_conv3d_workspace_size(
+        PRECISIONS[precision], view, N, Ti, Hi, Wi, Cin, Cout, C.byref(n)))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+
+
+def conv3d_fwd(x, w, b, view, shape_x, Cin, Cout, precision, resid=None):
+    """tok_op_conv3d_fwd.  x: chunked activations, or uint8 pixels (N,T,H,W,3)
+    when Cin = 3; returns chunked y, or dense float32 (N,To,Ho,Wo,3) when Cout = 3."""
+    N, Ti, Hi, Wi = shape_x
+    To, Ho, Wo = _view_out(view, Ti, Hi, Wi)
+    dev = w.device
+    if Cout == 3:
+        y = torch.empty((N, To, Ho, Wo, 3), dtype=torch.float32, device=dev)
+    else:
+        y = torch.empty(act_shape(N, To, Ho, Wo, Cout, precision), dtype=_OP_DTYPES[precision], device=dev)
+    ws = _conv_ws(precision, view, N, Ti, Hi, Wi, Cin, Cout, dev)
+    L.check("tok_op_conv3d_fwd", L.lib().tok_op_conv3d_fwd(
+        PRECISIONS[precision], view, _ptr(x), N, Ti, Hi, Wi, Cin, _ptr(w), _ptr(b), _ptr(resid), _ptr(y), Cout,
+        _ptr(ws), ws.numel(), _stream(dev)))
+    return y
+
+
+def conv3d_dgrad(dy, w, view, shape_x, Cin, Cout, precision):
+    """tok_op_conv3d_dgrad: dx (chunked, or dense float32 (N,T,H,W,3) when Cin = 3)."""
+    N, Ti, Hi, Wi = shape_x
+    dev = w.device
+    if Cin == 3:
+        dx = torch.empty((N, Ti, Hi, Wi, 3), dtype=torch.float32, device=dev)
+    else:
+        dx = torch.empty(act_shape(N, Ti, Hi, Wi, Cin, precision), dtype=_OP_DTYPES[precision], device=dev)
+    ws = _conv_ws(precision, view, N, Ti, Hi, Wi, Cin, Cout, dev)
+    L.check("tok_op_conv3d_dgrad", L.lib().tok_op_conv3d_dgrad(
+        PRECISIONS[precision], view, _ptr(dy), N, Ti, Hi, Wi, Cin, _ptr(w), _ptr(dx), Cout, _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return dx
+
+
+def conv3d_wgrad_op(x, dy, view, shape_x, Cin, Cout, precision, with_bias=True):
+    """tok_op_conv3d_wgrad: (dw float32 (Cout, Cin, 3, 3, 3), db float32 (Cout) or None)."""
+    N, Ti, Hi, Wi = shape_x
+    dev = dy.device
+    dw = torch.empty((Cout, Cin, 3, 3, 3), dtype=torch.float32, device=dev)
+    db = torch.empty(Cout, dtype=torch.float32, device=dev) if with_bias else None
+    ws = _conv_ws(precision, view, N, Ti, Hi, Wi, Cin, Cout, dev)
+    L.check("tok_op_conv3d_wgrad", L.lib().tok_op_conv3d_wgrad(
+        PRECISIONS[precision], view, _ptr(x), N, Ti, Hi, Wi, Cin, _ptr(dy), Cout, _ptr(dw), _ptr(db), _ptr(ws),
+        ws.numel(), _stream(dev)))
+    return dw, db
+
+
+def _gn_ws(precision, frames, HW, dev):
+    n = C.c_size_t()
+    L.check("tok_op_gn_workspace_size", L.lib().tok_op_gn_workspace_size(PRECISIONS[precision], frames, HW,
+                                                                         C.byref(n)))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+
+
+def _gn_dims(x):
+    N, T, _, H, W, _ = x.shape
+    return N * T, H * W
+
+
+def gn_stats(x, eps=1e-6):
+    """tok_op_gn_stats: (mean, rstd) float32 (frames, 32, 2) of a 64-channel chunked tensor."""
+    precision = _prec_of(x)
+    frames, HW = _gn_dims(x)
+    mr = torch.empty((frames, 32, 2), dtype=torch.float32, device=x.device)
+    ws = _gn_ws(precision, frames, HW, x.device)
+    L.check("tok_op_gn_stats", L.lib().tok_op_gn_stats(PRECISIONS[precision], _ptr(x), frames, HW, float(eps),
+                                                       _ptr(mr), _ptr(ws), ws.numel(), _stream(x.device)))
+    return mr
+
+
+def gn_apply(x, mr, gamma, beta):
+    """tok_op_gn_apply: SiLU(GroupNorm(x)) in x's layout."""
+    precision = _prec_of(x)
+    frames, HW = _gn_dims(x)
+    y = torch.empty_like(x)
+    ws = _gn_ws(precision, frames, HW, x.device)
+    L.check("tok_op_gn_apply", L.lib().tok_op_gn_apply(PRECISIONS[precision], _ptr(x), frames, HW, _ptr(mr),
+                                                       _ptr(gamma), _ptr(beta), _ptr(y), _ptr(ws), ws.numel(),
+                                                       _stream(x.device)))
+    return y
+
+
+def gn_bwd(x, dy, mr, gamma, beta, resid=None):
+    """tok_op_gn_bwd: (dx, dgamma, dbeta)."""
+    precision = _prec_of(x)
+    frames, HW = _gn_dims(x)
+    dx = torch.empty_like(x)
+    dg = torch.empty(64, dtype=torch.float32, device=x.device)
+    dbt = torch.empty(64, dtype=torch.float32, device=x.device)
+    ws = _gn_ws(precision, frames, HW, x.device)
+    L.check("tok_op_gn_bwd", L.lib().tok_op_gn_bwd(PRECISIONS[precision], _ptr(x), _ptr(dy), frames, HW, _ptr(mr),
+                                                   _ptr(gamma), _ptr(beta), _ptr(resid), _ptr(dx), _ptr(dg),
+                                                   _ptr(dbt), _ptr(ws), ws.numel(), _stream(x.device)))
+    return dx, dg, dbt
+
+
+def fsq_ste_bwd(z, gcodes, keep=None, gz_in=None):
+    """tok_op_fsq_ste_bwd: dL/dz of the straight-through quantiser."""
+    n = z.numel() // 6
+    gz = torch.empty_like(z)
+    L.check("tok_op_fsq_ste_bwd", L.lib().tok_op_fsq_ste_bwd(_ptr(z), _ptr(keep), _ptr(gcodes), _ptr(gz_in), n,
+                                                             _ptr(gz), _stream(z.device)))
+    return gz
+
+
+class Conv3dFn(torch.autograd.Function):
+    """Causal 3x3x3 conv with the library's adjoint kernels (tok_op_conv3d_*)."""
+
+    @staticmethod
+    def forward(ctx, x, w, b, view, shape_x, Cin, Cout, precision, resid=None):
+        w = w.detach().contiguous()
+        b = None if b is None else b.detach().contiguous()
+        y = conv3d_fwd(x.detach(), w, b, view, shape_x, Cin, Cout, precision,
+                       None if resid is None else resid.detach())
+        ctx.save_for_backward(x, w)
+        ctx.cfg = (view, tuple(shape_x), Cin, Cout, precision, b is not None, resid is not None)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w = ctx.saved_tensors
+        view, shape_x, Cin, Cout, precision, has_b, has_r = ctx.cfg
+        gy = gy.contiguous()
+        dx = None
+        if ctx.needs_input_grad[0] and Cin != 3:
+            dx = conv3d_dgrad(gy, w, view, shape_x, Cin, Cout, precision)
+        dw, db = conv3d_wgrad_op(x, gy, view, shape_x, Cin, Cout, precision, with_bias=has_b)
+        return dx, dw, db, None, None, None, None, None, (gy if has_r else None)
+
+
+class GroupNormSiLUFn(torch.autograd.Function):
+    """SiLU(GroupNorm(32)(x)) per frame on 64-channel chunked activations."""
+
+    @staticmethod
+    def forward(ctx, x, gamma, beta, eps=1e-6):
+        x = x.detach()
+        gamma, beta = gamma.detach().contiguous(), beta.detach().contiguous()
+        mr = gn_stats(x, eps)
+        ctx.save_for_backward(x, mr, gamma, beta)
+        return gn_apply(x, mr, gamma, beta)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, mr, gamma, beta = ctx.saved_tensors
+        dx, dg, db = gn_bwd(x, gy.contiguous(), mr, gamma, beta)
+        return dx, dg, db, None
+
+
+class FsqSTEFn(torch.autograd.Function):
+    """keep * FSQ(z) with the straight-through gradient (tok_quantize,
+    tok_drop with an external mask, tok_op_fsq_ste_bwd)."""
+
+    @staticmethod
+    def forward(ctx, z, keep=None):
+        z = z.detach().contiguous()
+        codes, _ = quantize(z)
+        if keep is not None:
+            N, T2, H2, W2, _ = codes.shape
+            drop(codes, Drop(mode=L.TOK_DROP_EXTERNAL, ext_keep=keep), keep=False)
+        ctx.save_for_backward(z, keep)
+        return codes
+
+    @staticmethod
+    def backward(ctx, gc):
+        z, keep = ctx.saved_tensors
+        return fsq_ste_bwd(z, gc.contiguous(), keep), None
 
 
 KERNEL_IDS = 23
