@@ -169,6 +169,24 @@ tok_status tok_select_workspace_size(int N, int T2, int H2, int W2, size_t* byte
 tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, int T2, int H2,
                               int W2, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* tok_select_similar without a workspace argument and without any device
+ * allocation, for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The selection's
+ * scratch (order keys, digit histograms, selection state) is a static device
+ * array of tok_select_scratch_bytes() bytes (32 MiB), one per GPU, held by
+ * each GPU the library runs on until the process ends; the call uses the
+ * array of the current device, so make the stream's device current.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (several streams, several host threads) race and give wrong results;
+ * serialise them.  Results equal tok_select_similar's bit for bit.  Batches
+ * whose tok_select_workspace_size exceeds the array are rejected with
+ * TOK_EWORKSPACE before anything is launched (e.g. 4 x 5 x 180 x 320 latents
+ * need 3.7 MB, 2 x 9 x 270 x 480 need 8.3 MB).  Other errors as
+ * tok_select_similar. */
+tok_status tok_select_scratch_bytes(size_t* bytes);
+tok_status tok_select_similar_noalloc(float rate, float* codes, uint8_t* keep, int N, int T2, int H2,
+                                      int W2, hipStream_t stream);
+
 /* ---- Token packets (Sec. 6.2) --------------------------------------------
  * The token matrices are sent row by row, one packet per row: a header with
  * the row number and a mask of the row's valid (not dropped) tokens, then the

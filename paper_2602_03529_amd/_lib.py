@@ -70,6 +70,10 @@ def lib():
     L.tok_select_workspace_size.argtypes = [i32, i32, i32, i32, C.POINTER(sz)]
     L.tok_select_similar.restype = i32
     L.tok_select_similar.argtypes = [C.c_float, vp, vp, i32, i32, i32, i32, vp, sz, vp]
+    L.tok_select_scratch_bytes.restype = i32
+    L.tok_select_scratch_bytes.argtypes = [C.POINTER(sz)]
+    L.tok_select_similar_noalloc.restype = i32
+    L.tok_select_similar_noalloc.argtypes = [C.c_float, vp, vp, i32, i32, i32, i32, vp]
     L.tok_packets_max_bytes.restype = i32
     L.tok_packets_max_bytes.argtypes = [i32, i32, i32, i32, C.POINTER(sz)]
     L.tok_packetize.restype = i32

@@ -755,6 +755,30 @@ tok_status tok_select_similar(float rate, float* codes, uint8_t* keep, int N, in
   return TOK_OK;
 }
 
+tok_status tok_select_similar_noalloc(float rate, float* codes, uint8_t* keep, int N, int T2, int H2, int W2,
+                                      hipStream_t s) {
+  if (!codes) return fail(TOK_EINVAL, "null codes");
+  if (N < 1 || T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
+  if (N > 65535 || (long long)T2 * H2 * W2 > 0x7fffffffLL)
+    return fail(TOK_ESHAPE, "need N <= 65535 and under 2^31 tokens per clip");
+  const size_t need = similarity_ws_bytes(N, T2, H2, W2);
+  if (need > kSimilarityScratchBytes)
+    return fail(TOK_EWORKSPACE, "selection needs " + std::to_string(need) + " bytes of scratch, the static scratch holds " +
+                                    std::to_string(kSimilarityScratchBytes));
+  if (reinterpret_cast<uintptr_t>(codes) & 7) return fail(TOK_EINVAL, "codes must be 8-byte aligned");
+  void* ws = nullptr;
+  TOK_HIP(similarity_scratch(&ws));
+  TOK_HIP(launch_similarity_drop(codes, keep, N, T2, H2, W2,
+                                 similarity_drop_count(rate, (long long)(T2 - 1) * H2 * W2), ws, s));
+  return TOK_OK;
+}
+
+tok_status tok_select_scratch_bytes(size_t* bytes) {
+  if (!bytes) return fail(TOK_EINVAL, "null argument");
+  *bytes = kSimilarityScratchBytes;
+  return TOK_OK;
+}
+
 namespace {
 
 tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, int W2, float* xhat, void* ws,

@@ -176,6 +176,10 @@ hipError_t launch_drop(const DropArgs& d, float* codes, uint8_t* keep, int N, in
 // from codes (N, T2, H2, W2, 6) in place and writes keep (or NULL).  ws holds
 // similarity_ws_bytes(N, T2, H2, W2) bytes (unused when D is 0 or every P token).
 size_t similarity_ws_bytes(int N, int T2, int H2, int W2);
+// Bytes of the per-device static selection scratch (tok_select_similar_noalloc),
+// and its address on the current device (taken once per device).
+constexpr size_t kSimilarityScratchBytes = (size_t)32 << 20;
+hipError_t similarity_scratch(void** ptr);
 // Row packets of Sec. 6.2 (format in packets.hip): the sender writes packet
 // offsets[g] .. offsets[g+1] of every row g and offsets[G] = stream length;
 // the receiver zero-fills codes / keep and scatters the packets at offsets.

@@ -18,6 +18,8 @@
 #include "tok_internal.h"
 #include "tok_device.h"
 
+#include <mutex>
+
 namespace tok {
 
 namespace {
@@ -247,6 +249,35 @@ size_t similarity_ws_bytes(int N, int T2, int H2, int W2) {
   auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
   return a((size_t)N * NP * 4) + a((size_t)N * kSelPasses * 256 * 4) + a((size_t)N * sizeof(SelState)) +
          a((size_t)N * kSelPasses * sizeof(SelState));
+}
+
+// Selection scratch for callers that cannot allocate: one array per GPU,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name is a stand-in, not a device address): each
+// device's address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+namespace {
+static __device__ __align__(256) unsigned char scratch[kSimilarityScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t similarity_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_similarity_drop(float* codes, uint8_t* keep, int N, int T2, int H2, int W2, long long D, void* ws,

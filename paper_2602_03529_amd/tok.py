@@ -608,6 +608,24 @@ def select_similar(codes: torch.Tensor, rate: float, keep=True, ws=None):
     return kp
 
 
+def select_scratch_bytes() -> int:
+    b = C.c_size_t()
+    L.check("tok_select_scratch_bytes", L.lib().tok_select_scratch_bytes(C.byref(b)))
+    return int(b.value)
+
+
+def select_similar_noalloc(codes: torch.Tensor, rate: float, keep=True):
+    """select_similar on the library's static per-GPU scratch (no workspace,
+    no device allocation by the library); calls on one GPU must not overlap."""
+    N, T2, H2, W2, _ = codes.shape
+    _need(codes, torch.float32, (N, T2, H2, W2, 6), "codes")
+    dev = codes.device
+    kp = torch.empty((N, T2, H2, W2), dtype=torch.uint8, device=dev) if keep else None
+    L.check("tok_select_similar_noalloc",
+            L.lib().tok_select_similar_noalloc(float(rate), _ptr(codes), _ptr(kp), N, T2, H2, W2, _stream(dev)))
+    return kp
+
+
 def packetize(idx: torch.Tensor, keep: torch.Tensor | None = None):
     """Row packets (Sec. 6.2) of FSQ indices (N,T2,H2,W2) int32 under keep:
     returns (buf uint8 of the worst-case length, offsets uint64 [N T2 H2 + 1];
