@@ -1,11 +1,24 @@
 """GPU tests of the fp8 decoder: e4m3 weights with per-output-channel fp32
 scales, MX-FP8 activations (e4m3 with one power-of-two scale per position and
 32 channels) into the scaled MFMA, fp32 accumulation and GroupNorm
-statistics, bf16 residual stream.  Decoding the FP64 oracle's codes, the
-reconstruction is compared with the oracle's (PSNR, peak 2, and max-abs
-error); the bound is a regression guard below the measured value (see
-FP8_MIN_PSNR_DB).  Batch invariance, causality and determinism
-hold exactly, as for the other precisions."""
+statistics, bf16 residual stream.
+
+Parity is against tests/fp8_reference.py, the oracle's decoder with its conv
+operands rounded by that rule and everything else in float64 (its rounding
+helpers and polyphase form are pinned in tests/test_fp8_reference.py).  The
+GPU's fp32 accumulation differs from that model by ~1e-6 relative; an e4m3
+operand sitting that close to a rounding boundary flips by one quantum (1/16
+of its magnitude), and such flips cascade through the 8 quantised convs, so
+two evaluations of the rule that differ only in summation rounding are
+~2% apart in relative L2 (measured on the CPU, in the test, by evaluating the
+model again with every conv sum perturbed by up to 3e-5 relative).  Bars,
+both derived from that spread at test time:
+  element-wise: PSNR(gpu; model) at most 3 dB below PSNR(perturbed; model);
+  accuracy: PSNR(gpu; FP64 oracle) within 0.1 dB of PSNR(model; oracle) (the
+  perturbed evaluations stay within ~0.02 dB; truncating instead of rounding
+  to nearest even in the model moves it by ~11 dB).
+Batch invariance, causality and determinism hold exactly, as for the other
+precisions."""
 import numpy as np
 import pytest
 
@@ -13,14 +26,14 @@ torch = pytest.importorskip("torch")
 
 import synth  # noqa: E402
 from oracle import tokenizer as O  # noqa: E402
+from tests import fp8_reference as F8  # noqa: E402
 from tests import gpu_common as G  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-# e4m3 keeps 4 significant bits against bf16's 8, so the fp8 decoder's error
-# is expected about 2^4 times the bf16 decoder's (24 dB below its 40.4 dB on
-# these clips); measured 17.7-17.8 dB.  The bound is a regression guard.
-FP8_MIN_PSNR_DB = 16.0
+PERTURB_REL = 3e-5          # ~10x the fp32 accumulation error of a 1728-term sum
+ELEMENTWISE_MARGIN_DB = 3.0
+ACCURACY_BAND_DB = 0.1
 
 
 @pytest.fixture(scope="module")
@@ -51,8 +64,18 @@ def test_fp8_decode_of_oracle_codes(models, seeds, T, H, W):
     rows = {p: (O.psnr(x, ref["xhat"]), float(np.abs(x - ref["xhat"]).max())) for p, x in out.items()}
     print("PSNR vs oracle (dB), max-abs:", rows, flush=True)
     assert np.isfinite(out["fp8"]).all()
-    assert rows["fp8"][0] >= FP8_MIN_PSNR_DB
     assert rows["f32"][1] <= G.F32_RECON_TOL
+    # the fp8 decode against the operand-rounding model of the same rule
+    p32 = G.weights(True)
+    model = F8.decode_fp8(ref["codes"], p32)
+    pert = F8.decode_fp8(ref["codes"], p32, noise=(np.random.default_rng(7), PERTURB_REL))
+    bar = O.psnr(pert, model) - ELEMENTWISE_MARGIN_DB
+    p_gpu_model = O.psnr(out["fp8"], model)
+    d_acc = rows["fp8"][0] - O.psnr(model, ref["xhat"])
+    print("fp8: PSNR vs rounding model %.2f dB (bar %.2f), vs oracle %.3f dB (model %.3f, difference %.4f)" %
+          (p_gpu_model, bar, rows["fp8"][0], O.psnr(model, ref["xhat"]), d_acc), flush=True)
+    assert p_gpu_model >= bar
+    assert abs(d_acc) <= ACCURACY_BAND_DB
 
 
 def test_fp8_batch_invariant_and_deterministic(models):
