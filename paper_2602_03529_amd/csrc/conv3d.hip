@@ -1085,18 +1085,22 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
 
 
 // ---------------------------------------------------------------------------
-// Weight gradient.  Block = 256 threads (4 waves); block b handles temporal tap
-// kt, a 32-channel slice of the input channels, a 64-channel slice of the
-// output channels and a contiguous share of the (clip, frame, tile) items.
-// Per item it stages the output-gradient tile (256 positions x 64 channels)
-// and the input halo (32 channels) in LDS, then runs fp32 16x16x4 MFMAs with
-// K = output positions: wave w accumulates output channels 16w..16w+15 x the
-// 32 input channels x the 9 spatial taps (18 accumulator blocks).
+// Weight gradient of fp32 operands.  Block = 256 threads (4 waves); block b
+// handles temporal tap kt, a 32-channel slice of the input channels, a
+// 64-channel slice of the output channels and a contiguous share of the
+// (clip, frame, tile) items.  Per item it stages the output-gradient tile
+// (TH x TW positions x 64 channels) and the input halo (32 channels) in LDS,
+// then runs fp32 16x16x4 MFMAs with K = output positions: wave w accumulates
+// output channels 16w..16w+15 x the 32 input channels x the 9 spatial taps
+// (18 accumulator blocks).  Staging uses 16-byte loads, all of an item's
+// issued before its first barrier (one load latency per item), and two
+// blocks fit on a CU (76 KB of LDS at most), so one block's staging overlaps
+// the other's MFMAs.
 // ---------------------------------------------------------------------------
 template <int VIEW> struct WGeo;
-template <> struct WGeo<CM_S1> { static constexpr int TH = 4, TW = 64, HH = TH + 2, HW = TW + 2; };
-template <> struct WGeo<CM_S2> { static constexpr int TH = 4, TW = 32, HH = 2 * TH + 1, HW = 2 * TW + 1; };
-template <> struct WGeo<CM_UP> { static constexpr int TH = 4, TW = 64, HH = TH / 2 + 2, HW = TW / 2 + 2; };
+template <> struct WGeo<CM_S1> { static constexpr int TH = 2, TW = 64, HH = TH + 2, HW = TW + 2; };
+template <> struct WGeo<CM_S2> { static constexpr int TH = 2, TW = 32, HH = 2 * TH + 1, HW = 2 * TW + 1; };
+template <> struct WGeo<CM_UP> { static constexpr int TH = 2, TW = 64, HH = TH / 2 + 2, HW = TW / 2 + 2; };
 
 template <int VIEW>
 __device__ __forceinline__ int wg_row(int r, int c, int kh, int kw) {
@@ -1106,18 +1110,15 @@ __device__ __forceinline__ int wg_row(int r, int c, int kh, int kw) {
   else return ((r + kh + 1) >> 1) * G::HW + ((c + kw + 1) >> 1);
 }
 
-template <int PREC>
-__device__ __forceinline__ float ld_elem(const void* base, size_t e) {
-  if constexpr (PREC == P_BF16) return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(base)[e] << 16);
-  else return reinterpret_cast<const float*>(base)[e];
-}
-
-template <int PREC, int VIEW>
-__global__ void __launch_bounds__(256) wgrad_kernel(WgradLaunch a) {
+template <int VIEW>
+__global__ void __launch_bounds__(256, 2) wgrad_kernel(WgradLaunch a) {
   using G = WGeo<VIEW>;
-  constexpr int CH = Op<PREC>::CH;
+  constexpr int CH = 16;                   // fp32 channels per 64-byte chunk
   constexpr int NPOS = G::TH * G::TW;      // output positions per item
   constexpr int HALO = G::HH * G::HW;
+  constexpr int NDYQ = NPOS * 16;          // dy float4s per item (64 channels)
+  constexpr int NXQ = HALO * 8;            // halo float4s per item (32 channels)
+  constexpr int DYK = (NDYQ + 255) / 256, XK = (NXQ + 255) / 256;
   __shared__ float s_dy[NPOS][64 + 1];
   __shared__ float s_x[HALO][32 + 1];
 
@@ -1142,6 +1143,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradLaunch a) {
   float bsum = 0.f;
 
   const size_t plane_x = (size_t)a.Hi * a.Wi, plane_y = (size_t)a.Ho * a.Wo;
+  const float4* dyq = reinterpret_cast<const float4*>(a.dy);
+  const float4* xq = reinterpret_cast<const float4*>(a.x);
   for (long long item = i0; item < i1; ++item) {
     long long u = item;
     const int tw = (int)(u % tiles_w); u /= tiles_w;
@@ -1153,42 +1156,58 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradLaunch a) {
     if constexpr (VIEW == CM_S1) ts = max(to + kt - 2, 0);
     else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
     else ts = (max(to + kt - 2, 0) + 1) >> 1;
-    __syncthreads();
-    // output-gradient tile: 64 channels starting at ot*64
-    for (int e = tid; e < NPOS * 64; e += 256) {
-      const int p = e >> 6, c = e & 63;
+    // all of the item's 16-byte loads first (zeros outside the frame and past
+    // the stored channels); element e = (chunk, position, quad), quad fastest
+    float4 vd[DYK], vx[XK];
+#pragma unroll
+    for (int k = 0; k < DYK; ++k) {
+      const int e = tid + 256 * k;
+      const int q = e & 3, p = (e >> 2) % NPOS, c4 = (e >> 2) / NPOS;
       const int oh = h0 + p / G::TW, ow = w0 + p % G::TW;
-      const int oc = ot * 64 + c;
-      float val = 0.f;
-      if (oh < a.Ho && ow < a.Wo && oc < a.Cout) {
-        const size_t off = (((size_t)n * a.To + to) * a.dy_chunks + oc / CH) * plane_y * CH +
-                           ((size_t)oh * a.Wo + ow) * CH + oc % CH;
-        val = ld_elem<PREC>(a.dy, off);
-      }
-      s_dy[p][c] = val;
+      const int ck = ot * 4 + c4;
+      vd[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NDYQ && oh < a.Ho && ow < a.Wo && ck < a.dy_chunks)
+        vd[k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + ck) * plane_y + (size_t)oh * a.Wo + ow) * 4 + q];
     }
-    // input halo: 32 channels starting at it*32, zero outside the frame
-    for (int e = tid; e < HALO * 32; e += 256) {
-      const int p = e >> 5, c = e & 31;
-      const int r = p / G::HW, q = p % G::HW;
+#pragma unroll
+    for (int k = 0; k < XK; ++k) {
+      const int e = tid + 256 * k;
+      const int q = e & 3, p = (e >> 2) % HALO, c2 = (e >> 2) / HALO;
+      const int r = p / G::HW, c = p % G::HW;
       int hs, ws;
-      if constexpr (VIEW == CM_S1) { hs = h0 - 1 + r; ws = w0 - 1 + q; }
-      else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + r; ws = 2 * w0 - 1 + q; }
-      else { hs = (h0 >> 1) - 1 + r; ws = (w0 >> 1) - 1 + q; }
-      const int icn = it * 32 + c;
-      float val = 0.f;
-      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && icn < a.Cin) {
-        const size_t off = (((size_t)n * a.Ti + ts) * a.x_chunks + icn / CH) * plane_x * CH +
-                           ((size_t)hs * a.Wi + ws) * CH + icn % CH;
-        val = ld_elem<PREC>(a.x, off);
+      if constexpr (VIEW == CM_S1) { hs = h0 - 1 + r; ws = w0 - 1 + c; }
+      else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + r; ws = 2 * w0 - 1 + c; }
+      else { hs = (h0 >> 1) - 1 + r; ws = (w0 >> 1) - 1 + c; }
+      const int ck = it * 2 + c2;
+      vx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NXQ && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ck < a.x_chunks)
+        vx[k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ck) * plane_x + (size_t)hs * a.Wi + ws) * 4 + q];
+    }
+    __syncthreads();  // the previous item's MFMAs are done with the tiles
+#pragma unroll
+    for (int k = 0; k < DYK; ++k) {
+      const int e = tid + 256 * k;
+      if (e < NDYQ) {
+        const int q = e & 3, p = (e >> 2) % NPOS, c4 = (e >> 2) / NPOS;
+        float* d = &s_dy[p][c4 * 16 + q * 4];
+        d[0] = vd[k].x; d[1] = vd[k].y; d[2] = vd[k].z; d[3] = vd[k].w;
       }
-      s_x[p][c] = val;
+    }
+#pragma unroll
+    for (int k = 0; k < XK; ++k) {
+      const int e = tid + 256 * k;
+      if (e < NXQ) {
+        const int q = e & 3, p = (e >> 2) % HALO, c2 = (e >> 2) / HALO;
+        float* d = &s_x[p][c2 * 16 + q * 4];
+        d[0] = vx[k].x; d[1] = vx[k].y; d[2] = vx[k].z; d[3] = vx[k].w;
+      }
     }
     __syncthreads();
     if (bias_sum && tid < 64) {
       for (int p = 0; p < NPOS; ++p) bsum += s_dy[p][tid];
     }
     // K = output positions, 4 per MFMA
+#pragma unroll 2
     for (int k0 = 0; k0 < NPOS; k0 += 4) {
       const int p = k0 + k4;
       const int r = p / G::TW, c = p % G::TW;
@@ -1573,19 +1592,11 @@ hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s) {
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }
-#define TOK_WG(P, V) hipLaunchKernelGGL((wgrad_kernel<P, V>), g, b, 0, s, a)
-  if (a.prec == P_BF16) {
-    if (a.view == CM_S1) TOK_WG(P_BF16, CM_S1);
-    else if (a.view == CM_S2) TOK_WG(P_BF16, CM_S2);
-    else if (a.view == CM_UP) TOK_WG(P_BF16, CM_UP);
-    else return hipErrorInvalidValue;
-  } else {
-    if (a.view == CM_S1) TOK_WG(P_F32, CM_S1);
-    else if (a.view == CM_S2) TOK_WG(P_F32, CM_S2);
-    else if (a.view == CM_UP) TOK_WG(P_F32, CM_UP);
-    else return hipErrorInvalidValue;
-  }
-#undef TOK_WG
+  if (a.prec != P_F32) return hipErrorInvalidValue;
+  if (a.view == CM_S1) hipLaunchKernelGGL(wgrad_kernel<CM_S1>, g, b, 0, s, a);
+  else if (a.view == CM_S2) hipLaunchKernelGGL(wgrad_kernel<CM_S2>, g, b, 0, s, a);
+  else if (a.view == CM_UP) hipLaunchKernelGGL(wgrad_kernel<CM_UP>, g, b, 0, s, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
