@@ -213,6 +213,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   __shared__ uint4 lds_w[NBUF][WQ];
   __shared__ uint16_t lds_sc[SCN];
   __shared__ __align__(16) float lds_px[PXN];
+  __shared__ float lds_lut[MODE == CM_I2C ? 256 : 1];
   constexpr int WQI = MODE == CM_I2C ? NT * 4 * (kI2cK / O::CH) : 1;  // im2col: every stage's weights
   __shared__ uint4 lds_wi[WQI];
   __shared__ float red[kWaves][32];
@@ -347,31 +348,48 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   // QE consecutive K entries k = (kt*9 + kh*3 + kw)*3 + c of one position.
   constexpr int PXW = G::TW + 2, PXH = G::TH + 2;
   auto stage_px = [&]() {
-    // The 3 x PXH row segments of PXW pixels (3 bytes each) as bytes: thread
-    // t handles bytes t, t + 256, ...; every load is issued before the first
-    // is used, so the tile waits for one memory latency, not one per pixel.
-    constexpr int SEG = PXW * 3, NBYTES = 3 * PXH * SEG, NB8 = (NBYTES + kThreads - 1) / kThreads;
-    uint32_t vb[NB8];
+    // The 3 x PXH row segments of PXW pixels (3 bytes each).  Thread t loads
+    // dwords t, t + 256, ... of the segments' 4-byte-aligned byte ranges with
+    // buffer loads over the pixel tensor (bytes before its start or past its
+    // end read as zeros), all issued before the first is used; the bytes are
+    // then normalised through a 256-entry table of x/127.5 - 1.
+    constexpr int SEG = PXW * 3, NSEG = 3 * PXH, DWS = (SEG + 6) / 4, NDW = NSEG * DWS;
+    constexpr int K = (NDW + kThreads - 1) / kThreads;
+    lds_lut[tid] = (float)tid / 127.5f - 1.0f;
+    const uint32_t nbytes = (uint32_t)((size_t)a.N * a.Ti * a.Hi * a.Wi * 3);  // < 2^31, checked on the host
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.in), (short)0, (int)nbytes, 0x00020000);
+    uint32_t vw[K];
+    long long sstart[K];
 #pragma unroll
-    for (int k = 0; k < NB8; ++k) {
-      const int b = tid + k * kThreads;
-      const int seg = b / SEG, o = b - seg * SEG;
+    for (int k = 0; k < K; ++k) {
+      const int d = tid + k * kThreads;
+      const int seg = d / DWS, dw = d - seg * DWS;
       const int f = seg / PXH, r = seg - f * PXH;
-      const int c = o / 3, ch = o - 3 * c;
-      const int hs = h0 - 1 + r, ws = w0 - 1 + c;
+      const int hs = h0 - 1 + r;
       const int g = max(a.go0 + to + f - 2, 0) - a.gi0;  // causal clamp of the input frame
-      vb[k] = 0x100u;  // outside the frame (or past the last byte): zero
-      if (b < NBYTES && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi)
-        vb[k] = reinterpret_cast<const uint8_t*>(a.in)[(((size_t)n * a.Ti + g) * a.Hi * a.Wi + (size_t)hs * a.Wi +
-                                                        ws) * 3 + ch];
+      sstart[k] = ((((long long)n * a.Ti + g) * a.Hi + hs) * a.Wi + (w0 - 1)) * 3;
+      const uint32_t off = (uint32_t)((sstart[k] & ~3LL) + 4 * dw);  // a negative start wraps past the end: zeros
+      vw[k] = 0u;
+      if (d < NDW && hs >= 0 && hs < a.Hi) vw[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
     }
+    __syncthreads();  // the table
 #pragma unroll
-    for (int k = 0; k < NB8; ++k) {
-      const int b = tid + k * kThreads;
-      if (b < NBYTES) {
-        const int seg = b / SEG, o = b - seg * SEG;
-        const int c = o / 3, ch = o - 3 * c;
-        lds_px[(seg * PXW + c) * 4 + ch] = vb[k] == 0x100u ? 0.f : (float)vb[k] / 127.5f - 1.0f;
+    for (int k = 0; k < K; ++k) {
+      const int d = tid + k * kThreads;
+      if (d >= NDW) continue;
+      const int seg = d / DWS, dw = d - seg * DWS;
+      const int hs = h0 - 1 + (seg - (seg / PXH) * PXH);
+      const bool row_ok = hs >= 0 && hs < a.Hi;
+      const int shift = (int)(sstart[k] & 3);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rel = 4 * dw + j - shift;  // byte of the segment
+        if (rel < 0 || rel >= SEG) continue;
+        const int c = rel / 3, ch = rel - 3 * c;
+        const int ws = w0 - 1 + c;
+        const bool ok = row_ok && ws >= 0 && ws < a.Wi;
+        lds_px[(seg * PXW + c) * 4 + ch] = ok ? lds_lut[(vw[k] >> (8 * j)) & 255u] : 0.f;
       }
     }
     for (int p = tid; p < 3 * PXH * PXW; p += kThreads) lds_px[p * 4 + 3] = 0.f;  // the 4th (zero) channel
@@ -878,11 +896,18 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
 
   // activation output: byte offset of this lane's 4 channels of block b at
   // position block m (the residual has the output's layout)
-  auto act_off = [&](int oh, int ow, int b) {
+  // (a per-block base: frame, channel chunk and the lane's channels; plus the
+  // position's 32-bit offset: a plane is below 2^31 bytes, checked on the host)
+  size_t cbase[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
     const int c0 = ct * NT + b * 16 + 4 * g4;
     const int chunk = c0 / OO::CH, within = c0 % OO::CH;
-    return (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
-           ((size_t)oh * a.Wo + ow) * kChunkBytes + (size_t)within * (kChunkBytes / OO::CH);
+    cbase[b] = (((size_t)n * a.To_buf + a.out_f0 + to) * a.out_chunks + chunk) * plane_out * kChunkBytes +
+               (size_t)within * (kChunkBytes / OO::CH);
+  }
+  auto act_off = [&](int oh, int ow, int b) {
+    return cbase[b] + (size_t)(uint32_t)((oh * a.Wo + ow) * kChunkBytes);
   };
   // bf16 residual: every value of this lane loaded before the first store,
   // without branches (past the frame edge: a clamped in-frame address whose
@@ -1549,6 +1574,10 @@ hipError_t dispatch_fp8(const ConvLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
+  // output positions are addressed with 32-bit offsets within a plane
+  if ((size_t)a.Ho * a.Wo * kChunkBytes >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+  // the first layer reads its uint8 pixels with 32-bit buffer offsets
+  if (a.in_kind == IN_U8 && (size_t)a.N * a.Ti * a.Hi * a.Wi * 3 >= ((size_t)1 << 31)) return hipErrorInvalidValue;
   if (a.stats && !(a.nt == 64 && a.Cout == 64 && a.cout_tiles == 1)) return hipErrorInvalidValue;
   // the epilogue reads the residual of every channel of its tile
   if (a.resid && (a.nt <= 0 || a.Cout % a.nt != 0)) return hipErrorInvalidValue;
