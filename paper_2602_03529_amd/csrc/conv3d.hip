@@ -188,7 +188,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 template <int PREC, int MODE, int NB, int IN_KIND, int OUT_KIND, bool RESID, bool STATS>
-__global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ? kI2cOcc : 2)
+__global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ? kI2cOcc
+                                           : (MODE == CM_S1 && OUT_KIND == OUT_RGB32 && PREC != P_FP8) ? 3 : 2)
     conv3d_kernel(ConvLaunch a) {
   using G = Geo<MODE>;
   using O = Op<PREC>;
@@ -209,8 +210,11 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   constexpr int PXN = MODE == CM_I2C ? 3 * (G::TH + 2) * (G::TW + 2) * 4 : 1;  // normalised pixel halo
   static_assert(MODE != CM_I2C || (IN_KIND == IN_U8 && !F8), "im2col: uint8 input");
 
+  // 64 -> 3 last layer (bf16 / fp32): rows-as-taps path below, weights staged compactly
+  constexpr bool RGBL = !F8 && MODE == CM_S1 && OUT_KIND == OUT_RGB32;
+  constexpr int WQR = 27 * 4;  // its weight quads per stage: 9 taps x 3 colours x 4 quads
   __shared__ uint4 lds_a[NBUF][HQ];
-  __shared__ uint4 lds_w[NBUF][WQ];
+  __shared__ uint4 lds_w[NBUF][RGBL ? 128 : WQ];
   __shared__ uint16_t lds_sc[SCN];
   __shared__ __align__(16) float lds_px[PXN];
   __shared__ float lds_lut[MODE == CM_I2C ? 256 : 1];
@@ -262,6 +266,26 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   if constexpr (MODE == CM_S1T) wset = (size_t)ct * 2 + (tg == 0 ? 1 : 0);
   const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + wset * G::KTS * a.in_chunks * WQ;
   const int nstages = G::KTS * a.in_chunks;  // stage = (temporal tap, input chunk)
+  // Order of the temporal taps: the blocks of neighbouring output frames run
+  // side by side (output frame is the fastest tile index after the channel
+  // tile), so each block takes its taps in an order in which neighbours read
+  // the same input frame in the same step and the second read is served by
+  // L2.  Stride 1: step j reads the input frame congruent to j mod 3 (shared
+  // by three neighbours); stride 2: even / odd output frames take taps
+  // (2, 0, 1) / (0, 2, 1) (frame 2t shared by t, t + 1 in step 0, frame 2t + 2
+  // by t + 1, t + 2 in step 1); upsampling: even / odd output frames (1, 0) /
+  // (0, 1) (source frame j shared by 2j, 2j + 1 in step 0).  The order
+  // depends on the global output frame only, so chunked and whole-clip runs
+  // still sum in the same order.
+  auto stage_of = [&](int j) {
+    const int jt = j / a.in_chunks, ck = j - jt * a.in_chunks;
+    int kt = jt;
+    if constexpr (MODE == CM_S1) kt = (jt + 5 - tg % 3) % 3;
+    else if constexpr (MODE == CM_S1T) kt = (jt + 3 - tg % 3) % 3;
+    else if constexpr (MODE == CM_S2) kt = jt == 2 ? 1 : ((tg & 1) ? 2 * jt : 2 - 2 * jt);
+    else if constexpr (MODE == CM_UPF) kt = (tg & 1) ? jt : 1 - jt;
+    return kt * a.in_chunks + ck;
+  };
 
   // Input buffer frame read by temporal tap kt (causal in global frame
   // numbers: frame 0 repeats for t < 0).
@@ -316,8 +340,17 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   auto issue_async = [&](int st, int buf) {
     const int kt = st / a.in_chunks, ck = st - kt * a.in_chunks;
     const uint4* wsrc = wbase + (size_t)st * WQ;
+    if constexpr (RGBL) {
+      // compact: row 3 tap + c of LDS <- packed row 16 tap + c (quads as packed, i.e. swizzled by the packed row)
+      const int e = wave * 64 + lane;
+      if (wave < 2 && e < WQR) {
+        const int r = e >> 2;
+        lds_dma16(wsrc + ((r / 3) * NT + r % 3) * 4 + (e & 3), &lds_w[buf][wave * 64]);
+      }
+    } else {
 #pragma unroll
-    for (int base = wave * 64; base < WQ; base += kThreads) lds_dma16(wsrc + base + lane, &lds_w[buf][base]);
+      for (int base = wave * 64; base < WQ; base += kThreads) lds_dma16(wsrc + base + lane, &lds_w[buf][base]);
+    }
     const uint4* src = reinterpret_cast<const uint4*>(a.in) +
                        (((size_t)n * a.Ti + src_frame(kt)) * a.in_chunks + ck) * plane_in * 4;
 #pragma unroll
@@ -585,7 +618,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     const int i0 = 4 * (wave >> 1), j0 = 32 * (wave & 1) + p32;
     for (int st = 0; st < nstages; ++st) {
       __syncthreads();
-      issue_async(st, 0);
+      issue_async(stage_of(st), 0);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
 #pragma unroll 1
@@ -798,6 +831,111 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     }
   }
 
+  // 64 -> 3 last layer (bf16 / fp32): the MFMA rows are (spatial tap, colour)
+  // pairs instead of output channels, 27 of 2 x 16 rows, and the columns are
+  // the halo positions.  Every stage (temporal tap, input chunk) accumulates
+  //   D[(kh, kw, c)][p] += sum_i W[c, i, kt, kh, kw] x[i, frame(kt), p]
+  // so the K loop needs 2 MFMAs per 16 halo positions instead of 9 taps x one
+  // 16-row block of which 3 rows are used; the epilogue then forms
+  //   y[c](i, j) = b[c] + sum_{kh, kw} D[(kh, kw, c)][(i + kh, j + kw)]
+  // through LDS, one kh at a time.
+  constexpr bool RGB = !F8 && MODE == CM_S1 && OUT_KIND == OUT_RGB32;
+  if constexpr (RGB) {
+    static_assert(NB == 1 && !RESID && !STATS, "3-channel output: one 16-row weight block, no residual or statistics");
+    constexpr int PB = (HALO + 15) / 16;              // halo position blocks
+    constexpr int KB = (PB + kWaves - 1) / kWaves;    // per wave: blocks wave, wave + 4, ...
+    f32x4 ar[KB][2];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) ar[k][0] = ar[k][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // this lane's A rows 16 rb + l16 = 3 tap + c (rows 27..31: zero): compact LDS row r, swizzled as packed row 16 tap + c
+    int wrow[2], wswz[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int r = 16 * rb + l16;
+      wrow[rb] = r < 27 ? r : -1;
+      wswz[rb] = swz((r / 3) * NT + r % 3);
+    }
+    for (int st = 0; st < nstages; ++st) {
+      __syncthreads();
+      issue_async(stage_of(st), 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      uint4 wq[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        wq[rb] = lds_w[0][max(wrow[rb], 0) * 4 + (g4 ^ wswz[rb])];
+        if (wrow[rb] < 0) wq[rb] = make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const int pb = wave + kWaves * k;
+        if (pb < PB) {  // uniform per wave
+          const int p = pb * 16 + l16, pc = min(p, HALO - 1);
+          uint4 aq = lds_a[0][pc * 4 + (g4 ^ swz(pc))];
+          if (p >= HALO) aq = make_uint4(0, 0, 0, 0);
+          mfma_quad<PREC>(ar[k][0], wq[0], aq);
+          mfma_quad<PREC>(ar[k][1], wq[1], aq);
+        }
+      }
+    }
+    // epilogue: thread t owns output positions t and t + 256 of the tile; D
+    // rows pass through the (then free) halo buffer
+    float* lds_d = reinterpret_cast<float*>(&lds_a[0][0]);
+    static_assert(9 * HALO * 4 <= HQ * 16, "one kh's D rows fit the halo buffer");
+    constexpr int NPOS = G::TH * G::TW / kThreads;
+    float o[NPOS][3];
+#pragma unroll
+    for (int u = 0; u < NPOS; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o[u][c] = lds_bias[c];
+#pragma unroll
+    for (int kh = 0; kh < 3; ++kh) {
+      __syncthreads();  // the K loop's / previous pass's LDS reads are done
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const int pb = wave + kWaves * k;
+        const int p = pb * 16 + l16;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int R = 16 * rb + 4 * g4 + r - 9 * kh;  // row within this kh's 9 rows (kw, c)
+            if (pb < PB && p < HALO && R >= 0 && R < 9) lds_d[R * HALO + p] = ar[k][rb][r];
+          }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NPOS; ++u) {
+        const int pos = tid + kThreads * u, i = pos / G::TW, j = pos % G::TW;
+        const float* d = lds_d + (i + kh) * G::HW + j;
+#pragma unroll
+        for (int kw = 0; kw < 3; ++kw)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) o[u][c] += d[(3 * kw + c) * HALO + kw];
+      }
+    }
+    const size_t plane_out = (size_t)a.Ho * a.Wo;
+#pragma unroll
+    for (int u = 0; u < NPOS; ++u) {
+      const int pos = tid + kThreads * u;
+      const int oh = h0 + pos / G::TW, ow = w0 + pos % G::TW;
+      if (oh >= a.Ho || ow >= a.Wo) continue;
+      float* op = reinterpret_cast<float*>(a.out) +
+                  (((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3;
+      if (a.blend_prev != nullptr && tg < a.blend_n) {
+        // frame i = tg + 1 of the GoP: a_i prev[Tp - n + i] + (1 - a_i) x_hat, a_i = (n - i) / n
+        const float al = (float)(a.blend_n - (tg + 1)) / (float)a.blend_n, be = 1.0f - al;
+        const float* pp = a.blend_prev + (((size_t)n * a.blend_Tp + (a.blend_Tp - a.blend_n + tg)) * plane_out +
+                                          (size_t)oh * a.Wo + ow) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[u][c] = al * pp[c] + be * o[u][c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) op[c] = o[u][c];
+    }
+    return;
+  }
+
   if constexpr (MODE == CM_I2C) {
     // pixels and all the weights once, then every K chunk without further staging
     stage_px();
@@ -807,7 +945,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     __syncthreads();
     for (int st = 0; st < nstages; ++st) compute_i2c(st);
   } else {
-    for (int st = 0; st < nstages; ++st) {
+    for (int j = 0; j < nstages; ++j) {
+      const int st = stage_of(j);
       if constexpr (MODE == CM_S1T) {
         if (src_frame(st / a.in_chunks) >= a.Ti) continue;  // beyond the last gradient frame (uniform per block)
       }
