@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # by the same counters on a 1 GiB device copy; see profiles/.  Valid for that
 # workload and the conv kernel as measured; other shapes report null, and so
 # does this one while the kernel has changed since the counters were taken.
-RB_CONV_HBM_BYTES_720P = 32.18e9
+RB_CONV_HBM_BYTES_720P = 22.45e9
 F32_PEAK_TFLOPS = 157.3
 # Useful FLOPs per output position of each conv (2 * taps * Cin * Cout) and
 # the level it runs at.  The 3x3x3 convs take 27 taps, except the upsampling
@@ -112,7 +112,7 @@ def oracle_params():
 
 
 def r1_leg(tok, synth, wflat, dev, args):
-    """configs[1]: 4 clips x 17 frames at 640x480 (seeds 0-3), the plain FP32
+    """The 640x480 accuracy workload: 4 clips x 17 frames (seeds 0-3), the plain FP32
     path and the BF16 path, each compared per clip with the FP64 oracle on
     the causal prefix of `r1_frames` output frames: output frames t < F
     depend on input frames < F only and latent frames < (F-1)/4 + 1 on the
@@ -242,7 +242,7 @@ DECODER_CONV_BYTES = {
 
 
 def fp8_leg(tok, synth, wflat, dev, args):
-    """configs[4]: decode-only, 2 clips x 33 frames at 1920x1080, fp8 vs bf16
+    """The 1080p decode workload: decode-only, 2 clips x 33 frames at 1920x1080, fp8 vs bf16
     vs f32 decoders on the latents of the clips' FP32 encode.  Accuracy: the
     FP64 oracle's round trip of clip 0's frame 0 (output frame 0 depends on
     latent frame 0 only, which depends on input frame 0 only), compared with
@@ -578,7 +578,7 @@ def main():
     if args.fp8_steps > 0:
         fp8 = fp8_leg(tok, synth, wflat, dev, args)
 
-    # ---- configs[1]: 4 x 17 x 640x480, FP32 and BF16 against the oracle -----
+    # ---- 4 x 17 x 640x480, FP32 and BF16 against the oracle ----------------
     r1 = None
     if args.r1_frames > 0:
         r1 = r1_leg(tok, synth, wflat, dev, args)
@@ -619,7 +619,7 @@ def main():
             if md is not mb:
                 md.close()
         psnr["decode_of_oracle_codes"] = dec
-        # single-thread figure: configs[0] (1 x 9 x 64x64) on one core
+        # single-thread figure: the small 1 x 9 x 64x64 clip on one core
         r0 = synth.make_batch([0], 9, 64, 64)
         with threadpool_limits(limits=1):
             t1 = time.perf_counter()
@@ -628,7 +628,7 @@ def main():
         cpu = dict(value=round(1.0 / dt, 6), unit="frames/s", cores=blas_threads(), kind="oracle",
                    sample="clip 0 frame 0 of the headline batch, full %dx%d FP64 round trip in %.1f s" % (W, H, dt),
                    cpu_model=cpu_model(), host_cores=host_cores(),
-                   single_thread=dict(sample="configs[0] clip, 1 x 9 x 64x64, FP64 round trip on one thread",
+                   single_thread=dict(sample="1 x 9 x 64x64 clip, FP64 round trip on one thread",
                                       seconds=round(dt1, 2),
                                       frames_per_s_720p_equivalent=round(9 * 64 * 64 / (W * H) / dt1, 6)))
         print("bench: oracle legs done (%.1f s, 1-thread %.1f s)" % (dt, dt1), file=sys.stderr, flush=True)
