@@ -1249,7 +1249,8 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
 
 
 // ---------------------------------------------------------------------------
-// Weight gradient of fp32 operands.  Block = 256 threads (4 waves); block b
+// Weight gradient of fp32 operands, stride 1 and stride 2 (the upsampling
+// view: wgrad_up_kernel below).  Block = 256 threads (4 waves); block b
 // handles temporal tap kt, a 32-channel slice of the input channels, a
 // 64-channel slice of the output channels and a contiguous share of the
 // (clip, frame, tile) items.  Per item it stages the output-gradient tile
@@ -1264,14 +1265,12 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
 template <int VIEW> struct WGeo;
 template <> struct WGeo<CM_S1> { static constexpr int TH = 2, TW = 64, HH = TH + 2, HW = TW + 2; };
 template <> struct WGeo<CM_S2> { static constexpr int TH = 2, TW = 32, HH = 2 * TH + 1, HW = 2 * TW + 1; };
-template <> struct WGeo<CM_UP> { static constexpr int TH = 2, TW = 64, HH = TH / 2 + 2, HW = TW / 2 + 2; };
 
 template <int VIEW>
 __device__ __forceinline__ int wg_row(int r, int c, int kh, int kw) {
   using G = WGeo<VIEW>;
   if constexpr (VIEW == CM_S1) return (r + kh) * G::HW + c + kw;
-  else if constexpr (VIEW == CM_S2) return (2 * r + kh) * G::HW + 2 * c + kw;
-  else return ((r + kh + 1) >> 1) * G::HW + ((c + kw + 1) >> 1);
+  else return (2 * r + kh) * G::HW + 2 * c + kw;
 }
 
 template <int VIEW>
@@ -1318,8 +1317,7 @@ __global__ void __launch_bounds__(256, 2) wgrad_kernel(WgradLaunch a) {
     const int h0 = th * G::TH, w0 = tw * G::TW;
     int ts;
     if constexpr (VIEW == CM_S1) ts = max(to + kt - 2, 0);
-    else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
-    else ts = (max(to + kt - 2, 0) + 1) >> 1;
+    else ts = max(2 * to + kt - 2, 0);
     // all of the item's 16-byte loads first (zeros outside the frame and past
     // the stored channels); element e = (chunk, position, quad), quad fastest
     float4 vd[DYK], vx[XK];
@@ -1340,8 +1338,7 @@ __global__ void __launch_bounds__(256, 2) wgrad_kernel(WgradLaunch a) {
       const int r = p / G::HW, c = p % G::HW;
       int hs, ws;
       if constexpr (VIEW == CM_S1) { hs = h0 - 1 + r; ws = w0 - 1 + c; }
-      else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + r; ws = 2 * w0 - 1 + c; }
-      else { hs = (h0 >> 1) - 1 + r; ws = (w0 >> 1) - 1 + c; }
+      else { hs = 2 * h0 - 1 + r; ws = 2 * w0 - 1 + c; }
       const int ck = it * 2 + c2;
       vx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (e < NXQ && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ck < a.x_chunks)
@@ -1400,6 +1397,150 @@ __global__ void __launch_bounds__(256, 2) wgrad_kernel(WgradLaunch a) {
 }
 
 // ---------------------------------------------------------------------------
+// Weight gradient of the upsampling conv (nearest x2 upsample, then the causal
+// 3x3x3 conv), fp32, in polyphase form.  Along each of t, h, w an output of
+// parity 0 reads, through the upsample, source offset -1 with tap 0 and offset
+// 0 with taps 1 and 2; parity 1 reads offset 0 with taps 0 and 1 and offset +1
+// with tap 2 (time: source frame ceil(u / 2), clamped at 0 like the conv's
+// causal padding).  The gradient is therefore accumulated per output phase
+// (pt, ph, pw) and source offset index (dt, dh, dw) in {0, 1}^3 -- 64 folded
+// taps, each over 1/8 of the output positions, 8 Cin Cout MACs per output
+// position instead of the dense view's 27 -- and the reduction unfolds them:
+// dW[kt, kh, kw] = sum over phases of the folded tap (kt, kh, kw) falls on.
+//   partial[split][fold][Cout][Cin], fold = ((((pt 2 + dt) 2 + ph) 2 + pw) 2 + dh) 2 + dw
+//   bias partial[split][pt 2 + ph][Cout]
+// Block = (pt, dt, ph, 32 input channels, 64 output channels, split).  An item
+// is kUpTM source rows m (output rows 2 m + ph) x 64 output columns (32 source
+// columns x both pw) of one output frame 2 j + pt; its positions are ordered
+// (row, pw, column), so the 4 positions of an MFMA's K share their phase.
+// Staging as in wgrad_kernel: every 16-byte load of an item issued before its
+// first barrier; the source halo is kUpTM + 2 rows x 34 columns.
+// ---------------------------------------------------------------------------
+constexpr int kUpTM = 2;
+
+__global__ void __launch_bounds__(256, 2) wgrad_up_kernel(WgradLaunch a) {
+  constexpr int TM = kUpTM, NPOS = TM * 64, HR = TM + 2, HC = 34, HALO = HR * HC;
+  constexpr int NDYQ = NPOS * 16;          // dy float4s per item (64 channels)
+  constexpr int NXQ = HALO * 8;            // halo float4s per item (32 channels)
+  constexpr int DYK = (NDYQ + 255) / 256, XK = (NXQ + 255) / 256;
+  __shared__ float s_dy[NPOS][64 + 1];
+  __shared__ float s_x[HALO][32 + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, k4 = lane >> 4;
+  const int ic_tiles = (a.Cin + 31) / 32, oc_tiles = (a.Cout + 63) / 64;
+  int v = blockIdx.x;
+  const int sp = v % a.splits; v /= a.splits;
+  const int ot = v % oc_tiles; v /= oc_tiles;
+  const int it = v % ic_tiles; v /= ic_tiles;
+  const int ph = v & 1, dt = (v >> 1) & 1, pt = v >> 2;
+  const int Tj = (a.To + 1 - pt) / 2;  // output frames 2 j + pt < To
+  const int tiles_m = (a.Hi + TM - 1) / TM, tiles_w = (a.Wo + 63) / 64;
+  const long long items = (long long)a.N * Tj * tiles_m * tiles_w;
+  const long long i0 = items * sp / a.splits, i1 = items * (sp + 1) / a.splits;
+
+  f32x4 acc[2][4][2];  // [pw][2 dh + dw][input-channel block]
+#pragma unroll
+  for (int pw = 0; pw < 2; ++pw)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[pw][f][0] = acc[pw][f][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool bias_sum = a.bpartial && dt == 0 && it == 0;
+  float bsum = 0.f;
+
+  const size_t plane_x = (size_t)a.Hi * a.Wi, plane_y = (size_t)a.Ho * a.Wo;
+  const float4* dyq = reinterpret_cast<const float4*>(a.dy);
+  const float4* xq = reinterpret_cast<const float4*>(a.x);
+  for (long long item = i0; item < i1; ++item) {
+    long long u = item;
+    const int tw = (int)(u % tiles_w); u /= tiles_w;
+    const int tm = (int)(u % tiles_m); u /= tiles_m;
+    const int j = (int)(u % Tj);
+    const int n = (int)(u / Tj);
+    const int to = 2 * j + pt;
+    const int m0 = tm * TM, w0 = tw * 64, q0 = w0 >> 1;
+    const int ts = max(j + dt - (pt ? 0 : 1), 0);  // source frame of temporal offset index dt
+    float4 vd[DYK], vx[XK];
+#pragma unroll
+    for (int k = 0; k < DYK; ++k) {
+      const int e = tid + 256 * k;
+      const int q = e & 3, p = (e >> 2) % NPOS, c4 = (e >> 2) / NPOS;
+      const int m = m0 + p / 64, ow = w0 + 2 * (p & 31) + ((p >> 5) & 1);
+      const int ck = ot * 4 + c4;
+      vd[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NDYQ && m < a.Hi && ow < a.Wo && ck < a.dy_chunks)
+        vd[k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + ck) * plane_y + (size_t)(2 * m + ph) * a.Wo + ow) * 4 + q];
+    }
+#pragma unroll
+    for (int k = 0; k < XK; ++k) {
+      const int e = tid + 256 * k;
+      const int q = e & 3, p = (e >> 2) % HALO, c2 = (e >> 2) / HALO;
+      const int hs = m0 - 1 + p / HC, ws = q0 - 1 + p % HC;
+      const int ck = it * 2 + c2;
+      vx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NXQ && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ck < a.x_chunks)
+        vx[k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ck) * plane_x + (size_t)hs * a.Wi + ws) * 4 + q];
+    }
+    __syncthreads();  // the previous item's MFMAs are done with the tiles
+#pragma unroll
+    for (int k = 0; k < DYK; ++k) {
+      const int e = tid + 256 * k;
+      if (e < NDYQ) {
+        const int q = e & 3, p = (e >> 2) % NPOS, c4 = (e >> 2) / NPOS;
+        float* d = &s_dy[p][c4 * 16 + q * 4];
+        d[0] = vd[k].x; d[1] = vd[k].y; d[2] = vd[k].z; d[3] = vd[k].w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < XK; ++k) {
+      const int e = tid + 256 * k;
+      if (e < NXQ) {
+        const int q = e & 3, p = (e >> 2) % HALO, c2 = (e >> 2) / HALO;
+        float* d = &s_x[p][c2 * 16 + q * 4];
+        d[0] = vx[k].x; d[1] = vx[k].y; d[2] = vx[k].z; d[3] = vx[k].w;
+      }
+    }
+    __syncthreads();
+    if (bias_sum && tid < 64) {
+      for (int p = 0; p < NPOS; ++p) bsum += s_dy[p][tid];
+    }
+    // K = 4 positions (r, pw, c0 + k4) per MFMA; source offset (dh, dw) of
+    // phase (ph, pw) reads halo row r + ph + dh, column c + pw + dw
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int pw = 0; pw < 2; ++pw)
+#pragma unroll 2
+        for (int c0 = 0; c0 < 32; c0 += 4) {
+          const int c = c0 + k4;
+          const float av = s_dy[r * 64 + pw * 32 + c][wave * 16 + l16];
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            const int row = (r + ph + (f >> 1)) * HC + c + pw + (f & 1);
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+              acc[pw][f][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, s_x[row][b * 16 + l16], acc[pw][f][b], 0, 0, 0);
+          }
+        }
+  }
+  // D block (o, i): lane holds o = 4 k4 + r (r = 0..3), i = l16
+#pragma unroll
+  for (int pw = 0; pw < 2; ++pw)
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int oc = ot * 64 + wave * 16 + 4 * k4 + r, icn = it * 32 + b * 16 + l16;
+          const int fold = ((((pt * 2 + dt) * 2 + ph) * 2 + pw) * 2 + (f >> 1)) * 2 + (f & 1);
+          if (oc < a.Cout && icn < a.Cin)
+            a.partial[(((size_t)sp * 64 + fold) * a.Cout + oc) * a.Cin + icn] = acc[pw][f][b][r];
+        }
+  if (bias_sum && tid < 64 && ot * 64 + tid < a.Cout)
+    a.bpartial[((size_t)sp * 4 + pt * 2 + ph) * a.Cout + ot * 64 + tid] = bsum;
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient on bf16 MFMA (bf16 operands; channel counts are padded to
 // 64-channel tiles, empty 16-channel blocks are skipped).
 // D[o][i] += dy[p][o] x~[p + tap][i] with K = output positions: 16x16x32 bf16
@@ -1410,16 +1551,23 @@ __global__ void __launch_bounds__(256, 2) wgrad_kernel(WgradLaunch a) {
 // operands need K (positions) contiguous in LDS, so dy and the input halo are
 // transposed while staged (8 x 8 register transposes, 16-byte LDS stores):
 //   s_dy[o][p], p = r * 64 + c;   s_x[i][row][plane][col]
-// with rows / columns of the conv's input as the tap sees it: stride 1 and
-// the upsampled view store the (upsampled) halo directly; stride 2 stores the
-// halo's even and odd columns in two planes.  The column read by tap kw is
-// then offset by 0, 1 or 2 elements from a 16-byte boundary; offset reads
-// take 5 dwords and realign them with byte shifts.
+// with rows / columns of the conv's input as the tap sees it: stride 1 stores
+// the halo directly; stride 2 stores the halo's even and odd columns in two
+// planes.  The column read by tap kw is then offset by 0, 1 or 2 elements
+// from a 16-byte boundary; offset reads take 5 dwords and realign them with
+// byte shifts.
+// The upsampling view (VIEW = CM_UPF) runs in polyphase form, as
+// wgrad_up_kernel does for fp32: block = (pt, dt, ph, ...), an item is TH
+// source rows m (output rows 2 m + ph) x 64 output columns of frame 2 j + pt,
+// its positions ordered (row, pw, column) so that a K step of 32 positions is
+// one (row, pw); the halo is the source's (TH + 2 rows x 34 columns), and
+// accumulator t = 4 pw + 2 dh + dw holds folded tap (pw, dh, dw), written to
+// the 64-tap partial layout (8 Cin Cout MACs per output position instead of 27).
 // ---------------------------------------------------------------------------
 template <int VIEW> struct WMGeo;
-template <> struct WMGeo<CM_S1> { static constexpr int TH = 2, ROWS = 4, PLANES = 1; };
-template <> struct WMGeo<CM_UP> { static constexpr int TH = 2, ROWS = 4, PLANES = 1; };
-template <> struct WMGeo<CM_S2> { static constexpr int TH = 1, ROWS = 3, PLANES = 2; };
+template <> struct WMGeo<CM_S1> { static constexpr int TH = 2, ROWS = 4, PLANES = 1, QB = 9; };
+template <> struct WMGeo<CM_UPF> { static constexpr int TH = 2, ROWS = 4, PLANES = 1, QB = 5; };
+template <> struct WMGeo<CM_S2> { static constexpr int TH = 1, ROWS = 3, PLANES = 2, QB = 9; };
 constexpr int kWmCols = 80;   // halo columns per plane row: >= 66, multiple of 8, + 8 for the read window
 
 template <int VIEW> struct WMLds {
@@ -1493,14 +1641,17 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
   const int sp = v % a.splits; v /= a.splits;
   const int ot = v % oc_tiles; v /= oc_tiles;
   const int it = v % ic_tiles; v /= ic_tiles;
-  const int kt = v;
-  const int tiles_h = (a.Ho + G::TH - 1) / G::TH, tiles_w = (a.Wo + 63) / 64;
+  constexpr bool UPF = VIEW == CM_UPF;
+  const int kt = v;                                       // dense views: temporal tap
+  const int ph = v & 1, dt = (v >> 1) & 1, pt = v >> 2;   // polyphase: output phase / offset index
+  const int Tj = UPF ? (a.To + 1 - pt) / 2 : a.To;        // output frames of the block
+  const int tiles_h = UPF ? (a.Hi + G::TH - 1) / G::TH : (a.Ho + G::TH - 1) / G::TH, tiles_w = (a.Wo + 63) / 64;
   const int nob = min(4, (a.Cout - ot * 64 + 15) / 16);      // output-channel blocks holding channels
   const bool wave_cols = it * 64 + wave * 16 < a.Cin;          // this wave's input channels exist
   const int dy_ch = a.dy_chunks * 32, x_ch = a.x_chunks * 32;  // channels stored (zeros past Cout / Cin)
-  const long long items = (long long)a.N * a.To * tiles_h * tiles_w;
+  const long long items = (long long)a.N * Tj * tiles_h * tiles_w;
   const long long i0 = items * sp / a.splits, i1 = items * (sp + 1) / a.splits;
-  const bool bias_sum = a.bpartial && kt == 0 && it == 0;
+  const bool bias_sum = a.bpartial && (UPF ? dt : kt) == 0 && it == 0;
   float bsum = 0.f;  // thread t: channel t >> 2, positions (t & 3) + 4 k of each item
   __shared__ float s_bias[4][64];
 
@@ -1517,20 +1668,21 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
     long long u = item;
     const int tw = (int)(u % tiles_w); u /= tiles_w;
     const int th = (int)(u % tiles_h); u /= tiles_h;
-    const int to = (int)(u % a.To); u /= a.To;
+    const int jt = (int)(u % Tj); u /= Tj;
     const int n = (int)u;
-    const int h0 = th * G::TH, w0 = tw * 64;
+    const int to = UPF ? 2 * jt + pt : jt;
+    const int h0 = th * G::TH, w0 = tw * 64;  // polyphase: h0 = first source row m0
     int ts;
     if constexpr (VIEW == CM_S1) ts = max(to + kt - 2, 0);
     else if constexpr (VIEW == CM_S2) ts = max(2 * to + kt - 2, 0);
-    else ts = (max(to + kt - 2, 0) + 1) >> 1;
+    else ts = max(jt + dt - (pt ? 0 : 1), 0);
     // ---- staging: dy in blocks of 8 positions x 8 output channels (position
     // block fastest across lanes: their transposed 16-byte stores hit distinct
     // banks), the input halo in blocks of 8 columns (of one plane row) x 8
     // input channels.  Thread t owns blocks t and t + 256 of the NDY + NHX and
     // issues all their global loads before the barrier, so an item waits for
     // one load latency, overlapped with the other waves' previous compute.
-    constexpr int QB = 9;  // column blocks holding the 66 halo columns
+    constexpr int QB = G::QB;  // column blocks holding the halo columns (66; polyphase 34)
     constexpr int NDY = (NPOS / 8) * 8, NHX = G::ROWS * G::PLANES * QB * 8;
     static_assert(NDY + NHX <= 512, "two staging blocks per thread");
     auto halo_block = [&](int hb, int* qb, int* cb, int* pl, int* hr) {
@@ -1551,7 +1703,8 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int p = pb * 8 + k;
-          const int oh = h0 + p / 64, ow = w0 + p % 64;
+          int oh = h0 + p / 64, ow = w0 + p % 64;
+          if constexpr (UPF) { oh = 2 * (h0 + p / 64) + ph; ow = w0 + 2 * (p & 31) + ((p >> 5) & 1); }
           if (oh < a.Ho && ow < a.Wo && oc < dy_ch)
             vv[r2][k] = dyq[((((size_t)n * a.To + to) * a.dy_chunks + oc / 32) * plane_y + (size_t)oh * a.Wo + ow) * 4 +
                             (oc % 32) / 8];
@@ -1566,12 +1719,8 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
           int hs, ws;
           if constexpr (VIEW == CM_S1) { hs = h0 - 1 + hr; ws = w0 - 1 + q; }
           else if constexpr (VIEW == CM_S2) { hs = 2 * h0 - 1 + hr; ws = 2 * w0 - 1 + 2 * q + pl; }
-          else {  // upsampled coordinates -> source
-            const int hu = h0 - 1 + hr, wu = w0 - 1 + q;
-            hs = hu < 0 ? -1 : hu >> 1;
-            ws = wu < 0 ? -1 : wu >> 1;
-          }
-          if (q < 66 && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ic < x_ch)
+          else { hs = h0 - 1 + hr; ws = (w0 >> 1) - 1 + q; }  // source rows / columns
+          if (q < (UPF ? 34 : 66) && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi && ic < x_ch)
             vv[r2][k] = xq[((((size_t)n * a.Ti + ts) * a.x_chunks + ic / 32) * plane_x + (size_t)hs * a.Wi + ws) * 4 +
                            (ic % 32) / 8];
         }
@@ -1614,6 +1763,22 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
         for (int b = 0; b < 4; ++b)
           if (b < nob) acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b], bv, acc[b][t], 0, 0, 0);
       };
+      if constexpr (UPF) {
+        // K step ks = (row pr, phase pw); offset (dh, dw) reads halo row pr + ph + dh,
+        // columns c + pw + dw of this lane's c = 8 g4 .. 8 g4 + 7
+#pragma unroll
+        for (int dh = 0; dh < 2; ++dh) {
+          const Win16 w = ld16_bf16(xrow, (pr + ph + dh) * kWmCols + 8 * g4);
+          if ((ks & 1) == 0) {
+            mma(2 * dh + 0, win_at<0>(w));
+            mma(2 * dh + 1, win_at<1>(w));
+          } else {
+            mma(4 + 2 * dh + 0, win_at<1>(w));
+            mma(4 + 2 * dh + 1, win_at<2>(w));
+          }
+        }
+        continue;
+      }
 #pragma unroll
       for (int kh = 0; kh < 3; ++kh) {
         if constexpr (VIEW == CM_S2) {
@@ -1637,18 +1802,22 @@ __global__ void __launch_bounds__(256, 2) wgrad_mfma_kernel(WgradLaunch a) {
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < (UPF ? 8 : 9); ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int oc = ot * 64 + b * 16 + 4 * g4 + r, icn = it * 64 + wave * 16 + l16;
-        if (oc < a.Cout && icn < a.Cin)
-          a.partial[((((size_t)sp * 3 + kt) * 9 + t) * a.Cout + oc) * a.Cin + icn] = acc[b][t][r];
+        // polyphase: folded tap ((((pt, dt), ph), pw = t / 4), dh, dw) of the 64
+        const size_t slot = UPF ? (size_t)sp * 64 + (((((pt * 2 + dt) * 2 + ph) * 2 + (t >> 2)) * 2 + ((t >> 1) & 1)) * 2 +
+                                                     (t & 1))
+                                : ((size_t)sp * 3 + kt) * 9 + t;
+        if (oc < a.Cout && icn < a.Cin) a.partial[(slot * a.Cout + oc) * a.Cin + icn] = acc[b][t][r];
       }
   if (bias_sum) {
     s_bias[tid & 3][tid >> 2] = bsum;
     __syncthreads();
+    const size_t bslot = UPF ? (size_t)sp * 4 + pt * 2 + ph : (size_t)sp;
     if (tid < 64 && ot * 64 + tid < a.Cout)
-      a.bpartial[(size_t)sp * a.Cout + ot * 64 + tid] = ((s_bias[0][tid] + s_bias[1][tid]) + s_bias[2][tid]) + s_bias[3][tid];
+      a.bpartial[bslot * a.Cout + ot * 64 + tid] = ((s_bias[0][tid] + s_bias[1][tid]) + s_bias[2][tid]) + s_bias[3][tid];
   }
 }
 
@@ -1676,6 +1845,41 @@ __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restri
   float acc = 0.f;
 #pragma unroll 8
   for (int s = 0; s < splits; ++s) acc += partial[(size_t)s * total + e];
+  dw[((size_t)o * Cin + i) * 27 + tap] = acc;
+}
+
+// The polyphase partials of wgrad_up_kernel unfolded into the canonical layout
+// and summed in split order (per split: the 8 output phases in (pt, ph, pw)
+// order); the bias over the 4 (pt, ph) partials of every split.
+__global__ void __launch_bounds__(256) wgrad_reduce_up_kernel(const float* __restrict__ partial,
+                                                               const float* __restrict__ bpartial, int splits,
+                                                               int Cout, int Cin, float* __restrict__ dw,
+                                                               float* __restrict__ db) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)Cout * Cin * 27;
+  if (e >= total) {
+    const size_t o = e - total;
+    if (o >= (size_t)Cout || !db) return;
+    float acc = 0.f;
+    for (int s = 0; s < 4 * splits; ++s) acc += bpartial[(size_t)s * Cout + o];
+    db[o] = acc;
+    return;
+  }
+  const int i = (int)(e % Cin);
+  const size_t r = e / Cin;
+  const int o = (int)(r % Cout), tap = (int)(r / Cout);  // tap = kt * 9 + kh * 3 + kw
+  const int kt = tap / 9, kh = (tap / 3) % 3, kw = tap % 3;
+  // offset index of tap k for output parity p: p = 0 -> (0, 1, 1), p = 1 -> (0, 0, 1)
+  auto off = [](int p, int k) { return p ? (k == 2 ? 1 : 0) : (k >= 1 ? 1 : 0); };
+  const size_t fold_stride = (size_t)Cout * Cin, oi = (size_t)o * Cin + i;
+  float acc = 0.f;
+  for (int s = 0; s < splits; ++s)
+#pragma unroll
+    for (int ph8 = 0; ph8 < 8; ++ph8) {
+      const int pt = ph8 >> 2, ph = (ph8 >> 1) & 1, pw = ph8 & 1;
+      const int fold = ((((pt * 2 + off(pt, kt)) * 2 + ph) * 2 + pw) * 2 + off(ph, kh)) * 2 + off(pw, kw);
+      acc += partial[((size_t)s * 64 + fold) * fold_stride + oi];
+    }
   dw[((size_t)o * Cin + i) * 27 + tap] = acc;
 }
 
@@ -1730,15 +1934,27 @@ namespace {
 bool wgrad_uses_mfma_bf16(int prec, int Cout, int Cin) { (void)Cout; (void)Cin; return prec == P_BF16; }
 }  // namespace
 
+namespace {
+bool wgrad_polyphase(int prec, int view) { (void)prec; return view == CM_UP; }
+}  // namespace
+
+int wgrad_partial_taps(int prec, int view) { return wgrad_polyphase(prec, view) ? 64 : 27; }
+int wgrad_bias_parts(int prec, int view) { return wgrad_polyphase(prec, view) ? 4 : 1; }
+
 int wgrad_blocks_per_split(int prec, int view, int Cout, int Cin) {
-  (void)view;
-  if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) return 3 * ((Cin + 63) / 64) * ((Cout + 63) / 64);
+  if (wgrad_uses_mfma_bf16(prec, Cout, Cin))
+    return (wgrad_polyphase(prec, view) ? 8 : 3) * ((Cin + 63) / 64) * ((Cout + 63) / 64);
+  if (wgrad_polyphase(prec, view)) return 8 * ((Cin + 31) / 32) * ((Cout + 63) / 64);
   return 3 * ((Cin + 31) / 32) * ((Cout + 63) / 64);
 }
 
 int wgrad_items(int prec, int view, int Cout, int Cin, int N, int To, int Ho, int Wo) {
   int th, tw;
-  if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) {
+  if (wgrad_polyphase(prec, view)) {
+    // items of one (pt, ph) class: TM source rows x 64 columns of the odd output frames
+    const int tm = wgrad_uses_mfma_bf16(prec, Cout, Cin) ? WMGeo<CM_UPF>::TH : kUpTM;
+    return N * (To / 2) * ((Ho / 2 + tm - 1) / tm) * ((Wo + 63) / 64);
+  } else if (wgrad_uses_mfma_bf16(prec, Cout, Cin)) {
     th = view == CM_S2 ? WMGeo<CM_S2>::TH : WMGeo<CM_S1>::TH;
     tw = 64;
   } else if (view == CM_S2) {
@@ -1756,23 +1972,29 @@ hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s) {
   if (wgrad_uses_mfma_bf16(a.prec, a.Cout, a.Cin)) {
     if (a.view == CM_S1) hipLaunchKernelGGL(wgrad_mfma_kernel<CM_S1>, g, b, 0, s, a);
     else if (a.view == CM_S2) hipLaunchKernelGGL(wgrad_mfma_kernel<CM_S2>, g, b, 0, s, a);
-    else if (a.view == CM_UP) hipLaunchKernelGGL(wgrad_mfma_kernel<CM_UP>, g, b, 0, s, a);
-    else return hipErrorInvalidValue;
+    else if (a.view == CM_UP) {
+      if (a.To != 2 * a.Ti - 1 || a.Ho != 2 * a.Hi || a.Wo != 2 * a.Wi) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(wgrad_mfma_kernel<CM_UPF>, g, b, 0, s, a);
+    } else return hipErrorInvalidValue;
     return hipGetLastError();
   }
   if (a.prec != P_F32) return hipErrorInvalidValue;
   if (a.view == CM_S1) hipLaunchKernelGGL(wgrad_kernel<CM_S1>, g, b, 0, s, a);
   else if (a.view == CM_S2) hipLaunchKernelGGL(wgrad_kernel<CM_S2>, g, b, 0, s, a);
-  else if (a.view == CM_UP) hipLaunchKernelGGL(wgrad_kernel<CM_UP>, g, b, 0, s, a);
-  else return hipErrorInvalidValue;
+  else if (a.view == CM_UP) {
+    if (a.To != 2 * a.Ti - 1 || a.Ho != 2 * a.Hi || a.Wo != 2 * a.Wi) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wgrad_up_kernel, g, b, 0, s, a);
+  } else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_wgrad_reduce(const float* partial, const float* bpartial, int splits, int Cout, int Cin, float* dw,
-                               float* db, hipStream_t s) {
-  const size_t total = (size_t)Cout * Cin * 27 + Cout;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, partial, bpartial,
-                     splits, Cout, Cin, dw, db);
+hipError_t launch_wgrad_reduce(const WgradLaunch& a, float* dw, float* db, hipStream_t s) {
+  const size_t total = (size_t)a.Cout * a.Cin * 27 + a.Cout;
+  const dim3 g((unsigned)((total + 255) / 256)), b(256);
+  if (wgrad_polyphase(a.prec, a.view))
+    hipLaunchKernelGGL(wgrad_reduce_up_kernel, g, b, 0, s, a.partial, a.bpartial, a.splits, a.Cout, a.Cin, dw, db);
+  else
+    hipLaunchKernelGGL(wgrad_reduce_kernel, g, b, 0, s, a.partial, a.bpartial, a.splits, a.Cout, a.Cin, dw, db);
   return hipGetLastError();
 }
 

@@ -59,17 +59,22 @@ struct WgradLaunch {
   int Cout, Cin;
   int view, prec;
   int splits;
-  float* partial;     // [splits][3][9][Cout][Cin]
-  float* bpartial;    // [splits][Cout] or null
+  float* partial;     // [splits][taps][Cout][Cin], taps = wgrad_partial_taps(prec, view)
+  float* bpartial;    // [splits][wgrad_bias_parts(prec, view)][Cout] or null
 };
 // Blocks per split, and work items (output tiles) shared among the splits,
 // of the weight-gradient launch for these operands: bf16 operands with Cin
 // and Cout multiples of 64 run on bf16 MFMA, everything else on fp32 MFMA.
 int wgrad_blocks_per_split(int prec, int view, int Cout, int Cin);
 int wgrad_items(int prec, int view, int Cout, int Cin, int N, int To, int Ho, int Wo);
+// Partial sums per split: wgrad_partial_taps(...) x [Cout][Cin] floats of
+// weights (27 taps, or 64 folded taps of the polyphase upsampling view) and
+// wgrad_bias_parts(...) x [Cout] of bias.
+int wgrad_partial_taps(int prec, int view);
+int wgrad_bias_parts(int prec, int view);
 hipError_t launch_wgrad(const WgradLaunch& a, hipStream_t s);
-hipError_t launch_wgrad_reduce(const float* partial, const float* bpartial, int splits, int Cout, int Cin, float* dw,
-                               float* db, hipStream_t s);
+// Sums a launch's partials (in split order) into dw [Cout][Cin][3][3][3] and db.
+hipError_t launch_wgrad_reduce(const WgradLaunch& a, float* dw, float* db, hipStream_t s);
 
 // Frames are addressed in windows so that a clip can be processed in causal
 // temporal chunks: a buffer holds Tb frames per clip, its frame 0 is global

@@ -78,8 +78,8 @@ ConvOpWs conv_op_ws(int P, int view, int N, int Ti, int Hi, int Wi, int Cin, int
   const int per = wgrad_blocks_per_split(P, wm, Cout, Cin);
   const int items = wgrad_items(P, wm, Cout, Cin, N, To, Ho, Wo);
   w.splits = std::max(1, std::min(items, std::max(1, 2048 / per)));
-  w.wp = align256((size_t)w.splits * 27 * Cout * Cin * 4);
-  w.wbp = align256((size_t)w.splits * Cout * 4);
+  w.wp = align256((size_t)w.splits * wgrad_partial_taps(P, wm) * Cout * Cin * 4);
+  w.wbp = align256((size_t)w.splits * wgrad_bias_parts(P, wm) * Cout * 4);
   w.total = w.pk + w.zeros + w.stats + w.tmp + w.wp + w.wbp;
   return w;
 }
@@ -266,7 +266,7 @@ tok_status tok_op_conv3d_wgrad(tok_precision prec, int view, const void* x, int 
   g.partial = ws_wp(a);
   g.bpartial = ws_wbp(a);
   TOK_HIP(launch_wgrad(g, s));
-  TOK_HIP(launch_wgrad_reduce(g.partial, g.bpartial, g.splits, Cout, Cin, dw, db, s));
+  TOK_HIP(launch_wgrad_reduce(g, dw, db, s));
   return TOK_OK;
 }
 

@@ -93,8 +93,8 @@ TrainPlan make_train_plan(const Dims& d, int prec) {
   for (const WgradShape& w : wgrad_shapes(d)) {
     const ConvSpec& c = kConv[w.layer];
     const size_t sp = wgrad_splits(prec, w.view, c.cout, c.cin, d.N, w.To, w.Ho, w.Wo);
-    wp = std::max(wp, sp * 27 * c.cout * c.cin);
-    wbp = std::max(wbp, sp * c.cout);
+    wp = std::max(wp, sp * wgrad_partial_taps(prec, w.view) * c.cout * c.cin);
+    wbp = std::max(wbp, sp * wgrad_bias_parts(prec, w.view) * c.cout);
   }
   p.WP = take(wp * 4); p.WBP = take(wbp * 4);
   p.GNP = take(gn_bwd_partial_floats((int)frames, d.H * d.W, prec) * 4);
@@ -181,8 +181,7 @@ tok_status wgrad(const TrainCtx& c, int l, int view, const void* x, int Ti, int 
   Timed tm(c.m, K_WGRAD, c.s);
   hipError_t e = launch_wgrad(a, c.s);
   if (e == hipSuccess)
-    e = launch_wgrad_reduce(a.partial, a.bpartial, a.splits, cs.cout, cs.cin, dweights + c.m->w_off[l],
-                            dweights + c.m->b_off[l], c.s);
+    e = launch_wgrad_reduce(a, dweights + c.m->w_off[l], dweights + c.m->b_off[l], c.s);
   if (e != hipSuccess) return fail(TOK_EDEVICE, "wgrad layer " + std::to_string(l) + ": " + hipGetErrorString(e));
   return TOK_OK;
 }
@@ -473,7 +472,8 @@ bool wgrad_op_shape(int view, int N, int Ti, int Hi, int Wi, int To, int Ho, int
 int view_mode(int view) { return view == 0 ? CM_S1 : (view == 1 ? CM_S2 : (view == 2 ? CM_UP : -1)); }
 size_t wgrad_op_bytes(int P, int mode, int N, int To, int Ho, int Wo, int Cin, int Cout, int* splits) {
   *splits = wgrad_splits(P, mode, Cout, Cin, N, To, Ho, Wo);
-  return align256((size_t)*splits * 27 * Cout * Cin * 4) + align256((size_t)*splits * Cout * 4);
+  return align256((size_t)*splits * wgrad_partial_taps(P, mode) * Cout * Cin * 4) +
+         align256((size_t)*splits * wgrad_bias_parts(P, mode) * Cout * 4);
 }
 }  // namespace
 
@@ -504,9 +504,10 @@ tok_status tok_conv3d_wgrad(tok_precision prec, int view, const void* x, int N, 
   a.dy = dy; a.To = To; a.Ho = Ho; a.Wo = Wo; a.dy_chunks = cdiv(Cout, CH);
   a.Cout = Cout; a.Cin = Cin; a.view = mode; a.prec = P; a.splits = sp;
   a.partial = static_cast<float*>(ws);
-  a.bpartial = reinterpret_cast<float*>(static_cast<char*>(ws) + align256((size_t)sp * 27 * Cout * Cin * 4));
+  a.bpartial = reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                       align256((size_t)sp * wgrad_partial_taps(P, mode) * Cout * Cin * 4));
   TOK_HIP(launch_wgrad(a, s));
-  TOK_HIP(launch_wgrad_reduce(a.partial, a.bpartial, sp, Cout, Cin, dw, db, s));
+  TOK_HIP(launch_wgrad_reduce(a, dw, db, s));
   return TOK_OK;
 }
 

@@ -81,6 +81,22 @@ def test_wgrad_matches_oracle(tk, prec, view, cin, cout):
     assert e_w <= REL_L2 and e_b <= REL_L2
 
 
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_wgrad_upsample_ragged_rows_and_single_odd_frame(tk, prec):
+    """Upsampling view with an odd source height (a partial row pair at the
+    bottom), a ragged last column tile and Ti = 2 (one odd output frame)."""
+    cin, cout = 128, 64
+    xs, ys = (1, 2, 5, 33), (1, 3, 10, 66)
+    x = storage_round(synth.randn(71, xs + (cin,)), prec)
+    dy = storage_round(synth.randn(72, ys + (cout,)), prec)
+    gw, gb = B.conv3d_wgrad(O.upsample(x.astype(np.float64)), dy.astype(np.float64), (cout, cin, 3, 3, 3))
+    dw, db = tk.conv3d_wgrad(to_chunked(x, prec), to_chunked(dy, prec), xs, ys, cin, cout, 2, prec)
+    torch.cuda.synchronize()
+    e_w, e_b = rel_l2(dw.cpu().numpy(), gw), rel_l2(db.cpu().numpy(), gb)
+    print(prec, "up ragged rel-L2 dw %.2e db %.2e" % (e_w, e_b), flush=True)
+    assert e_w <= REL_L2 and e_b <= REL_L2
+
+
 def test_wgrad_rejects_mismatched_shapes(tk):
     from paper_2602_03529_amd._lib import TokError
     x = torch.zeros((1, 5, 2, 8, 8, 32), dtype=torch.bfloat16, device="cuda")
