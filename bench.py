@@ -409,6 +409,33 @@ def coding_leg(tok, x, xhat, codes, idx, args):
     return out
 
 
+def gemm_ceiling(n):
+    """The part's practical dense bf16 MFMA rate under sustained load: the
+    vendor library's (hipBLASLt, through torch.matmul) n x n x n bf16 GEMM,
+    timed like the conv kernels.  Context for the roofline fraction of a
+    power-limited part; nothing in the hot path uses it."""
+    import torch
+    a = torch.randn(n, n, dtype=torch.bfloat16, device="cuda")
+    b = torch.randn(n, n, dtype=torch.bfloat16, device="cuda")
+    c = torch.empty(n, n, dtype=torch.bfloat16, device="cuda")
+    for _ in range(5):
+        torch.matmul(a, b, out=c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    iters = 20
+    e0.record()
+    for _ in range(iters):
+        torch.matmul(a, b, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    del a, b, c
+    torch.cuda.empty_cache()
+    return dict(workload="torch.matmul bf16 %dx%dx%d (hipBLASLt)" % (n, n, n), ms=round(ms, 4),
+                tflops=round(tf, 1), frac_of_peak=round(tf / BF16_PEAK_TFLOPS, 4))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +461,8 @@ def main():
     ap.add_argument("--coding", type=int, default=1, help="1: time the coding steps on the headline batch")
     ap.add_argument("--select-rate", type=float, default=0.3, help="drop rate of the similarity selection leg")
     ap.add_argument("--residual-theta", type=float, default=0.03, help="residual threshold of the coding leg")
+    ap.add_argument("--gemm-ceiling", type=int, default=8192,
+                    help="n of the n^3 bf16 library GEMM timed as the part's practical MFMA rate (0 skips it)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -633,6 +662,12 @@ def main():
                                       frames_per_s_720p_equivalent=round(9 * 64 * 64 / (W * H) / dt1, 6)))
         print("bench: oracle legs done (%.1f s, 1-thread %.1f s)" % (dt, dt1), file=sys.stderr, flush=True)
 
+    if args.gemm_ceiling > 0:
+        ceiling = gemm_ceiling(args.gemm_ceiling)
+        ceiling["rb_conv_vs_gemm"] = round(roofline["achieved"] / ceiling["tflops"], 4)
+        roofline["library_gemm_tflops"] = ceiling["tflops"]
+    else:
+        ceiling = None
     line = dict(metric=METRIC, value=round(value, 3), unit="frames/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(ms_b, 3), higher_is_better=True, scaling="weak",
                 vs_baseline=None, dtype="bf16", data="synthetic",
@@ -644,7 +679,7 @@ def main():
                 achieved_tflops=round(total_flops / (ms_b / 1e3) / 1e12, 2),
                 conv_layers=conv_layers,
                 roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, r1=r1, train=train, fp8=fp8,
-                coding=coding, per_kernel=per_kernel)
+                coding=coding, mfma_ceiling=ceiling, per_kernel=per_kernel)
     print(json.dumps(line), flush=True)
 
 
