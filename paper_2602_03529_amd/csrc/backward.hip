@@ -289,39 +289,9 @@ __global__ void __launch_bounds__(256) gn_bwd_apply_kernel(const void* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint helpers.  Zero insertion (the adjoint of keeping every second output
-// of a stride-1 conv, i.e. a stride-2 conv): fine[n, 2t, 2h, 2w] = coarse[n, t,
-// h, w], zero elsewhere.  Upsample adjoint: coarse[n, j, h, w] = sum of fine
-// frames {2j-1, 2j} (just 0 for j = 0) x the 2 x 2 pixels.  One thread per
-// fine (resp. coarse) 64-byte chunk position.
+// Upsample adjoint: coarse[n, j, h, w] = sum of fine frames {2j-1, 2j} (just 0
+// for j = 0) x the 2 x 2 pixels.  One thread per coarse 64-byte chunk position.
 // ---------------------------------------------------------------------------
-template <int PREC>
-__global__ void __launch_bounds__(256) zero_insert_kernel(const void* __restrict__ coarse, void* __restrict__ fine,
-                                                           int N, int Tf, int Hf, int Wf, int chunks) {
-  constexpr int QE = E<PREC>::QE;
-  const size_t total = (size_t)N * Tf * chunks * Hf * Wf;
-  const size_t gid = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= total) return;
-  size_t r = gid;
-  const int w = (int)(r % Wf); r /= Wf;
-  const int h = (int)(r % Hf); r /= Hf;
-  const int ck = (int)(r % chunks); r /= chunks;
-  const int t = (int)(r % Tf);
-  const int n = (int)(r / Tf);
-  const int Tc = (Tf - 1) / 2 + 1, Hc = Hf / 2, Wc = Wf / 2;
-  float v[4 * QE];
-  if (((t | h | w) & 1) == 0) {
-    const size_t cq = ((((size_t)n * Tc + t / 2) * chunks + ck) * Hc + h / 2) * Wc + w / 2;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) load_quad<PREC>(coarse, cq * 4 + q, v + q * QE);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4 * QE; ++i) v[i] = 0.f;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) store_quad<PREC>(fine, gid * 4 + q, v + q * QE);
-}
-
 template <int PREC>
 __global__ void __launch_bounds__(256) up_adjoint_kernel(const void* __restrict__ fine, void* __restrict__ coarse,
                                                           int N, int Tc, int Hc, int Wc, int chunks) {
@@ -526,14 +496,6 @@ hipError_t launch_gn_bwd(const void* x, const void* g, const float2* mr, const f
   hipLaunchKernelGGL(gn_bwd_param_kernel, dim3(1), dim3(64), 0, s, fsum, frames, dgamma, dbeta);
   TOK_PREC_LAUNCH(gn_bwd_apply_kernel, dim3((HW + 63) / 64, frames * chunks), dim3(256), x, g, mr, m12, gamma, beta,
                   resid, dx, HW);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_insert(const void* coarse, void* fine, int N, int Tf, int Hf, int Wf, int chunks, int prec,
-                              hipStream_t s) {
-  if ((Tf - 1) % 2 != 0 || Hf % 2 != 0 || Wf % 2 != 0) return hipErrorInvalidValue;
-  const size_t total = (size_t)N * Tf * chunks * Hf * Wf;
-  TOK_PREC_LAUNCH(zero_insert_kernel, dim3(nblk(total, 256)), dim3(256), coarse, fine, N, Tf, Hf, Wf, chunks);
   return hipGetLastError();
 }
 

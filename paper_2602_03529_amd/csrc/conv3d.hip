@@ -69,6 +69,8 @@ template <> struct Geo<CM_UPF> {
   static constexpr int WR = 0, TW = 64, TH = 8, HH = TH / 2 + 2, HW = TW / 2 + 2;
   static constexpr int MB = (TH / 2) * (TW / 2 / 16), WT = 16, KTS = 2;
 };
+// The stride-2 adjoint runs on the polyphase path (coarse gradient as source).
+template <> struct Geo<CM_S2T> : Geo<CM_UPF> {};
 
 // Stride-1 modes give each wave a 4 x 32 sub-tile (waves 2 x 2 over the 8 x 64
 // workgroup tile): an activation operand loaded for halo row r then serves
@@ -85,7 +87,7 @@ __device__ __forceinline__ void out_local(int wave, int m, int l16, int* i, int*
   if constexpr (MODE == CM_S1 || MODE == CM_S1T || MODE == CM_I2C) {
     *i = 4 * (wave >> 1) + (m >> 1);
     *j = 32 * (wave & 1) + 16 * (m & 1) + l16;
-  } else if constexpr (MODE == CM_UPF) {
+  } else if constexpr (MODE == CM_UPF || MODE == CM_S2T) {
     *i = 2 * (m >> 1) + (wave >> 1);
     *j = 2 * ((m & 1) * 16 + l16) + (wave & 1);
   } else {
@@ -122,7 +124,7 @@ __device__ __forceinline__ void halo_src(int p, int h0, int w0, int* hs, int* ws
     const int c = (pc < G::TW + 1) ? 2 * pc : 2 * (pc - (G::TW + 1)) + 1;
     *hs = 2 * h0 - 1 + r;
     *ws = 2 * w0 - 1 + c;
-  } else {  // CM_UPF: source rows / columns of the upsampled tile
+  } else {  // CM_UPF / CM_S2T: source rows / columns of the tile
     *hs = (h0 >> 1) - 1 + r;
     *ws = (w0 >> 1) - 1 + pc;
   }
@@ -264,6 +266,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   size_t wset = ct;
   if constexpr (MODE == CM_UPF) wset = (size_t)ct * 2 + (tg & 1);
   if constexpr (MODE == CM_S1T) wset = (size_t)ct * 2 + (tg == 0 ? 1 : 0);
+  // stride-2 adjoint: output frame 0 (causal clamp), even, odd output frames
+  if constexpr (MODE == CM_S2T) wset = (size_t)ct * 3 + (tg == 0 ? 0 : ((tg & 1) ? 2 : 1));
   const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + wset * G::KTS * a.in_chunks * WQ;
   const int nstages = G::KTS * a.in_chunks;  // stage = (temporal tap, input chunk)
   // Order of the temporal taps: the blocks of neighbouring output frames run
@@ -284,6 +288,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     else if constexpr (MODE == CM_S1T) kt = (jt + 3 - tg % 3) % 3;
     else if constexpr (MODE == CM_S2) kt = jt == 2 ? 1 : ((tg & 1) ? 2 * jt : 2 - 2 * jt);
     else if constexpr (MODE == CM_UPF) kt = (tg & 1) ? jt : 1 - jt;
+    else if constexpr (MODE == CM_S2T) kt = (tg & 1) ? jt : 1 - jt;  // frame j + 1 shared by 2 j, 2 j + 1 in step 0
     return kt * a.in_chunks + ck;
   };
 
@@ -293,6 +298,12 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     int g;
     if constexpr (MODE == CM_S1) g = max(tg + kt - 2, 0);
     else if constexpr (MODE == CM_S1T) g = tg + kt;  // gradient frames t, t+1, t+2 (past the end: none)
+    else if constexpr (MODE == CM_S2T) {
+      // output frame 2 j reads gradient frames j (forward tap 2) and j + 1 (tap 0), frame 2 j + 1 frame
+      // j + 1 (tap 1) only; its second stage has no taps (reported as past the end)
+      const int jt = tg >> 1;
+      g = (tg & 1) ? (kt == 0 ? jt + 1 : a.gi0 + a.Ti) : jt + kt;
+    }
     else if constexpr (MODE == CM_S2) g = max(2 * tg + kt - 2, 0);
     else {
       // even output frame 2j reads source frames j-1 (clamped) and j; odd 2j+1 reads j and j+1
@@ -435,7 +446,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       // tap 2 pr + (g4 >> 1), channel quads h, 2 + h; the scale this lane
       // supplies is that of tap 2 pr + (g4 & 1), 32-channel block g4 >> 1.
       const int h = g4 & 1, sblk = g4 >> 1;
-      if constexpr (MODE == CM_UPF) {
+      if constexpr (MODE == CM_UPF || MODE == CM_S2T) {
         const int ph = wave >> 1, pw = wave & 1;
 #pragma unroll 1
         for (int pr = 0; pr < 2; ++pr) {
@@ -480,7 +491,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       }
       return;
     }
-    if constexpr (MODE == CM_UPF) {
+    if constexpr (MODE == CM_UPF || MODE == CM_S2T) {
       const int ph = wave >> 1, pw = wave & 1;
 #pragma unroll
       for (int tap = 0; tap < 4; ++tap) {
@@ -947,7 +958,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   } else {
     for (int j = 0; j < nstages; ++j) {
       const int st = stage_of(j);
-      if constexpr (MODE == CM_S1T) {
+      if constexpr (MODE == CM_S1T || MODE == CM_S2T) {
         if (src_frame(st / a.in_chunks) >= a.Ti) continue;  // beyond the last gradient frame (uniform per block)
       }
       __syncthreads();
@@ -1237,6 +1248,10 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   }
   if (a.mode == CM_S1T) {
     if (!res && !st) return launch_one<PREC, CM_S1T, 4, IN_ACT, OUT_ACT, false, false>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.mode == CM_S2T) {
+    if (!res && !st) return launch_one<PREC, CM_S2T, 4, IN_ACT, OUT_ACT, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_UPF) {
@@ -1924,6 +1939,9 @@ hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
   if (a.stats && !(a.nt == 64 && a.Cout == 64 && a.cout_tiles == 1)) return hipErrorInvalidValue;
   // the epilogue reads the residual of every channel of its tile
   if (a.resid && (a.nt <= 0 || a.Cout % a.nt != 0)) return hipErrorInvalidValue;
+  // the stride-2 adjoint maps a coarse gradient to its fine-resolution input shape
+  if (a.mode == CM_S2T && (a.To != 2 * a.Ti - 1 || a.Ho != 2 * a.Hi || a.Wo != 2 * a.Wi || a.gi0 != 0))
+    return hipErrorInvalidValue;
   if (a.prec == P_BF16) return dispatch_prec<P_BF16>(a, s);
   if (a.prec == P_F32) return dispatch_prec<P_F32>(a, s);
   if (a.prec == P_FP8) return dispatch_fp8(a, s);
@@ -2008,6 +2026,12 @@ hipError_t launch_wgrad_reduce(const WgradLaunch& a, float* dw, float* db, hipSt
 // followed by a 3-tap kernel is, for output parity 0, tap 0 on source offset
 // -1 and taps 1+2 on offset 0; for parity 1, taps 0+1 on offset 0 and tap 2 on
 // offset +1.
+// Stride-2 adjoint layout (CM_S2T), as CM_UPF's with three weight sets (output
+// frame 0, even, odd output frames) and, per dimension, parity 0 holding tap 1
+// on source offset 0 (offset -1: zero), parity 1 tap 2 on offset 0 and tap 0 on
+// offset +1; in time, set 0 holds taps 0 + 1 + 2 on gradient frame 0 and tap 0
+// on frame 1, set 1 tap 2 on frame j and tap 0 on frame j + 1, set 2 tap 1 on
+// frame j + 1 (and nothing on its second stage).  Channels as in CM_S1T.
 // Adjoint layout (CM_S1T), per adjoint output tile ct and weight set:
 //   [ct][set][dt][chunk][kh*3+kw][o][quad][QE]
 // with adjoint output channel o = forward input channel, adjoint input channel
@@ -2053,6 +2077,29 @@ __device__ float pack_value(const float* __restrict__ w, const PackGeom& g, size
     for (int kt = fold_lo(pt, dt); kt <= fold_hi(pt, dt); ++kt)
       for (int kh = fold_lo(ph, dh); kh <= fold_hi(ph, dh); ++kh)
         for (int kw = fold_lo(pw, dw); kw <= fold_hi(pw, dw); ++kw) v += W(co, ci, kt, kh, kw);
+    return v;
+  }
+  if (g.mode == CM_S2T) {
+    const int tap = (int)(e % 4); e /= 4;
+    const int phase = (int)(e % 4); e /= 4;
+    const int ck = (int)(e % g.chunks); e /= g.chunks;
+    const int dt = (int)(e % 2); e /= 2;
+    const int set = (int)(e % 3); e /= 3;
+    const int ct = (int)e;
+    const int row = (phase * 4 + tap) * g.nt + o;
+    const int q = pq ^ swz(row);
+    const int oc = ct * g.nt + o, ic = ck * g.CH + q * g.QE + x;  // adjoint out / in channels
+    if (oc >= g.Cin || ic >= g.Cout) return 0.f;
+    // forward tap of parity p, source offset index d (offsets -1, 0 / 0, +1): -1 for none
+    auto s2t = [](int p, int d) { return p == 0 ? (d == 0 ? -1 : 1) : (d == 0 ? 2 : 0); };
+    const int kh = s2t(phase >> 1, tap >> 1), kw = s2t(phase & 1, tap & 1);
+    if (kh < 0 || kw < 0) return 0.f;
+    int k0, k1;  // forward temporal taps summed on this stage
+    if (set == 0) { k0 = 0; k1 = dt == 0 ? 2 : 0; }
+    else if (set == 1) { k0 = k1 = dt == 0 ? 2 : 0; }
+    else { if (dt == 1) return 0.f; k0 = k1 = 1; }
+    float v = 0.f;
+    for (int kt = k0; kt <= k1; ++kt) v += W(ic, oc, kt, kh, kw);
     return v;
   }
   if (g.mode == CM_I2C) {
@@ -2146,13 +2193,15 @@ PackGeom pack_geom(int Cout, int Cin, int prec, int mode, size_t* elems) {
   g.Cout = Cout; g.Cin = Cin; g.mode = mode;
   g.CH = prec == P_BF16 ? 32 : (prec == P_FP8 ? 64 : 16);
   g.QE = g.CH / 4;
-  const int co = mode == CM_S1T ? Cin : Cout;   // the adjoint maps Cout channels to Cin channels
-  const int ci = mode == CM_S1T ? Cout : Cin;
+  const bool adj = mode == CM_S1T || mode == CM_S2T;
+  const int co = adj ? Cin : Cout;   // the adjoints map Cout channels to Cin channels
+  const int ci = adj ? Cout : Cin;
   g.co = co;
   g.nt = co >= 64 ? 64 : 16;
   g.chunks = (ci + g.CH - 1) / g.CH;
   if (mode == CM_I2C) g.chunks = kI2cK / g.CH;  // K = 27 taps x 4 channels, padded
   if (mode == CM_UPF) g.R = 2 * 2 * g.chunks * 16;
+  else if (mode == CM_S2T) g.R = 3 * 2 * g.chunks * 16;
   else if (mode == CM_S1T) g.R = 2 * 3 * g.chunks * 9;
   else if (mode == CM_I2C) g.R = g.chunks;
   else g.R = 3 * g.chunks * 9;
@@ -2175,7 +2224,7 @@ hipError_t launch_pack_weights(const float* w, int Cout, int Cin, int prec, int 
   size_t n;
   const PackGeom g = pack_geom(Cout, Cin, prec, mode, &n);
   if (prec == P_FP8) {
-    if (!wscale || mode == CM_S1T) return hipErrorInvalidValue;
+    if (!wscale || mode == CM_S1T || mode == CM_S2T) return hipErrorInvalidValue;
     hipLaunchKernelGGL(wscale_kernel, dim3(g.co), dim3(256), 0, s, w, g, g.R, wscale);
     hipLaunchKernelGGL(pack_kernel<P_FP8>, dim3((unsigned)((n / 4 + 255) / 256)), dim3(256), 0, s, w, g, n, dst,
                        (const float*)wscale);

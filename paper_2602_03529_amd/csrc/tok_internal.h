@@ -27,7 +27,12 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 // taps x 4 (the 4th channel zero, so a tap is one 16-byte LDS read) padded to
 // 128, and the layer runs as a single-tap product with ~7x fewer MFMAs than
 // 27 taps of a 3-channel (padded) chunk.
-enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3, CM_S1T = 4, CM_I2C = 5 };
+// CM_S2T: the adjoint of a stride-2 causal conv, coarse gradient in, fine
+// gradient out, in the polyphase form of CM_UPF (one wave per output phase,
+// 2 x 2 x 2 source offsets per output; along each of t, h, w an output of
+// parity 0 takes tap 1 from offset 0, parity 1 taps 2 and 0 from offsets 0
+// and +1), instead of zero insertion and the dense stride-1 adjoint.
+enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3, CM_S1T = 4, CM_I2C = 5, CM_S2T = 6 };
 constexpr int kI2cK = 128;  // 27 taps x 4 channels, padded to whole 32-element bf16 chunks
 enum InKind { IN_ACT = 0, IN_U8 = 1 };
 // OUT_ACT: chunked activations of the kernel's output precision (bf16 for
@@ -237,9 +242,6 @@ hipError_t launch_loss_final(const float* l1p, int nl1, const float* cp, int nc,
 hipError_t launch_gn_bwd(const void* x, const void* g, const float2* mr, const float* gamma, const float* beta,
                          const void* resid, void* dx, int frames, int HW, int prec, float* partial, float2* fsum,
                          float2* m12, float* dgamma, float* dbeta, hipStream_t s);
-// fine[n, 2t, 2h, 2w] = coarse[n, t, h, w], zero elsewhere (adjoint of a stride-2 subsampling).
-hipError_t launch_zero_insert(const void* coarse, void* fine, int N, int Tf, int Hf, int Wf, int chunks, int prec,
-                              hipStream_t s);
 // Adjoint of the nearest x2 upsample (time map t -> ceil(t / 2)).
 hipError_t launch_up_adjoint(const void* fine, void* coarse, int N, int Tc, int Hc, int Wc, int chunks, int prec,
                              hipStream_t s);

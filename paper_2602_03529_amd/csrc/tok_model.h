@@ -54,6 +54,9 @@ inline int conv_mode(int l) {
   return CM_S1;
 }
 
+// Mode of each 3x3x3 layer's input-gradient conv (the packed adjoint kernel).
+inline int adj_mode(int l) { return conv_mode(l) == CM_S2 ? CM_S2T : CM_S1T; }
+
 constexpr float kGnEps = 1e-6f;
 constexpr float kCommitWeight = 0.1f;
 

@@ -62,14 +62,13 @@ ConvOpWs conv_op_ws(int P, int view, int N, int Ti, int Hi, int Wi, int Cin, int
   ConvOpWs w{};
   const size_t es = elem_bytes(P);
   const size_t pf = packed_conv_elems(Cout, Cin, P, fwd_mode(view, Cin), &w.nt);
-  const size_t pa = packed_conv_elems(Cout, Cin, P, CM_S1T, &w.ntT);
+  const size_t pa = packed_conv_elems(Cout, Cin, P, view == 1 ? CM_S2T : CM_S1T, &w.ntT);
   w.pk = align256(std::max(pf, pa) * es);
   w.zeros = align256((size_t)std::max(Cin, Cout) * 4);
   const size_t tiles = (size_t)cdiv(Ho, 8) * cdiv(Wo, 64);
   w.stats = Cin == 3 ? align256((size_t)N * To * tiles * 32 * sizeof(float4)) : 0;
   // fine-resolution temporaries of the adjoints and one-chunk copies of 3-channel operands
   size_t tmp = 0;
-  if (view == 1) tmp = (size_t)N * Ti * Hi * Wi * cdiv(Cout, chan_chunk(P)) * kChunkBytes;
   if (view == 2) tmp = (size_t)N * To * Ho * Wo * cdiv(Cin, chan_chunk(P)) * kChunkBytes;
   if (Cout == 3) tmp = (size_t)N * To * Ho * Wo * kChunkBytes;
   if (Cin == 3) tmp = (size_t)N * Ti * Hi * Wi * kChunkBytes;
@@ -214,7 +213,7 @@ tok_status tok_op_conv3d_dgrad(tok_precision prec, int view, const void* dy, int
   TOK_TRY(conv_op_check(prec, view, N, Ti, Hi, Wi, Cin, Cout, ws, ws_bytes, &a));
   if ((Cout != 3 && !al16(dy)) || (Cin != 3 && !al16(dx))) return fail(TOK_EINVAL, "activations must be 16-byte aligned");
   const int CH = chan_chunk(a.P);
-  TOK_HIP(launch_pack_weights(w, Cout, Cin, a.P, CM_S1T, ws_pk(a), nullptr, s));
+  TOK_HIP(launch_pack_weights(w, Cout, Cin, a.P, view == 1 ? CM_S2T : CM_S1T, ws_pk(a), nullptr, s));
   TOK_HIP(launch_fill_zero(ws_zeros(a), (size_t)Cin, s));
   const int out_kind = Cin == 3 ? OUT_RGB32 : OUT_ACT;
   const void* g = dy;
@@ -227,10 +226,9 @@ tok_status tok_op_conv3d_dgrad(tok_precision prec, int view, const void* dy, int
     TOK_HIP(run_conv(a, CM_S1T, ws_pk(a), ws_zeros(a), a.w.ntT, Cout, Cin, g, IN_ACT, Ti, Hi, Wi, dx, out_kind, Ti,
                      Hi, Wi, nullptr, nullptr, s));
   } else if (view == 1) {
-    // stride 2 = stride 1 then subsampling: zero insertion, then the stride-1 adjoint
-    TOK_HIP(launch_zero_insert(g, ws_tmp(a), N, Ti, Hi, Wi, cdiv(Cout, CH), a.P, s));
-    TOK_HIP(run_conv(a, CM_S1T, ws_pk(a), ws_zeros(a), a.w.ntT, Cout, Cin, ws_tmp(a), IN_ACT, Ti, Hi, Wi, dx,
-                     OUT_ACT, Ti, Hi, Wi, nullptr, nullptr, s));
+    // stride 2: the polyphase adjoint, coarse gradient in, fine gradient out
+    TOK_HIP(run_conv(a, CM_S2T, ws_pk(a), ws_zeros(a), a.w.ntT, Cout, Cin, g, IN_ACT, a.To, a.Ho, a.Wo, dx, OUT_ACT,
+                     Ti, Hi, Wi, nullptr, nullptr, s));
   } else {
     // upsample then stride-1 conv: the stride-1 adjoint at the fine resolution, then the upsample adjoint
     TOK_HIP(run_conv(a, CM_S1T, ws_pk(a), ws_zeros(a), a.w.ntT, Cout, Cin, g, IN_ACT, a.To, a.Ho, a.Wo, ws_tmp(a),

@@ -167,6 +167,14 @@ tok_status adj(const TrainCtx& c, int l, const void* gy, int T, int H, int W, vo
                gx, out_kind, T, H, W, nullptr, nullptr);
 }
 
+// Input gradient of layer l's stride-2 conv: coarse gradient (Tc, Hc, Wc) in,
+// fine gradient (2 Tc - 1, 2 Hc, 2 Wc) out, in polyphase form.
+tok_status adj_s2(const TrainCtx& c, int l, const void* gy, int Tc, int Hc, int Wc, void* gx) {
+  const tok_model* m = c.m;
+  return tconv(c, K_DGRAD, CM_S2T, m->wpkT[l], m->zeros, m->ntT[l], kConv[l].cout, kConv[l].cin, gy, IN_ACT, Tc, Hc,
+               Wc, gx, OUT_ACT, 2 * Tc - 1, 2 * Hc, 2 * Wc, nullptr, nullptr);
+}
+
 tok_status wgrad(const TrainCtx& c, int l, int view, const void* x, int Ti, int Hi, int Wi, const void* dy, int To,
                  int Ho, int Wo, float* dweights) {
   const ConvSpec& cs = kConv[l];
@@ -408,18 +416,10 @@ tok_status backward_impl(tok_model* m, const uint8_t* x, int N, int T, int H, in
   }
   // down2: stride-2 conv = stride-1 conv then subsampling
   TOK_TRY(wgrad(c, L_DOWN2, CM_S2, c.at(p.D1), d.T1, d.H1, d.W1, c.at(p.G2b), d.T2, d.H2, d.W2, dweights));
-  {
-    Timed tm(m, K_BWD_MISC, s);
-    TOK_HIP(launch_zero_insert(c.at(p.G2b), c.at(p.G1a), N, d.T1, d.H1, d.W1, wide_chunks, m->prec, s));
-  }
-  TOK_TRY(adj(c, L_DOWN2, c.at(p.G1a), d.T1, d.H1, d.W1, c.at(p.G1b), OUT_ACT));
+  TOK_TRY(adj_s2(c, L_DOWN2, c.at(p.G2b), d.T2, d.H2, d.W2, c.at(p.G1b)));
   // down1
   TOK_TRY(wgrad(c, L_DOWN1, CM_S2, c.at(p.E2), T, H, W, c.at(p.G1b), d.T1, d.H1, d.W1, dweights));
-  {
-    Timed tm(m, K_BWD_MISC, s);
-    TOK_HIP(launch_zero_insert(c.at(p.G1b), WIDE, N, T, H, W, wide_chunks, m->prec, s));
-  }
-  TOK_TRY(adj(c, L_DOWN1, WIDE, T, H, W, GB, OUT_ACT));
+  TOK_TRY(adj_s2(c, L_DOWN1, c.at(p.G1b), d.T1, d.H1, d.W1, GB));
   // encoder residual blocks, conv_in
   TOK_TRY(rb_backward(c, L_E_RB2_A, N_E_RB2_A, c.at(p.E1), dweights));
   TOK_TRY(rb_backward(c, L_E_RB1_A, N_E_RB1_A, c.at(p.H0), dweights));
