@@ -218,7 +218,11 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   __shared__ uint4 lds_a[NBUF][HQ];
   __shared__ uint4 lds_w[NBUF][RGBL ? 128 : WQ];
   __shared__ uint16_t lds_sc[SCN];
-  __shared__ __align__(16) float lds_px[PXN];
+  // im2col pixel tile: fp32 values, or for bf16 their bf16 bits (4 channels =
+  // 8 bytes a pixel, so an operand half is one 8-byte read, no conversion)
+  constexpr bool PXH16 = MODE == CM_I2C && PREC == P_BF16;
+  __shared__ __align__(16) float lds_px[PXH16 ? 1 : PXN];
+  __shared__ __align__(16) uint16_t lds_pxh[PXH16 ? PXN : 1];
   __shared__ float lds_lut[MODE == CM_I2C ? 256 : 1];
   constexpr int WQI = MODE == CM_I2C ? NT * 4 * (kI2cK / O::CH) : 1;  // im2col: every stage's weights
   __shared__ uint4 lds_wi[WQI];
@@ -399,7 +403,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     // then normalised through a 256-entry table of x/127.5 - 1.
     constexpr int SEG = PXW * 3, NSEG = 3 * PXH, DWS = (SEG + 6) / 4, NDW = NSEG * DWS;
     constexpr int K = (NDW + kThreads - 1) / kThreads;
-    lds_lut[tid] = (float)tid / 127.5f - 1.0f;
+    lds_lut[tid] = (float)tid / 127.5f - 1.0f;  // (bf16: read back rounded to nearest even)
     const uint32_t nbytes = (uint32_t)((size_t)a.N * a.Ti * a.Hi * a.Wi * 3);  // < 2^31, checked on the host
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.in), (short)0, (int)nbytes, 0x00020000);
@@ -433,10 +437,15 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
         const int c = rel / 3, ch = rel - 3 * c;
         const int ws = w0 - 1 + c;
         const bool ok = row_ok && ws >= 0 && ws < a.Wi;
-        lds_px[(seg * PXW + c) * 4 + ch] = ok ? lds_lut[(vw[k] >> (8 * j)) & 255u] : 0.f;
+        const float v = ok ? lds_lut[(vw[k] >> (8 * j)) & 255u] : 0.f;
+        if constexpr (PXH16) lds_pxh[(seg * PXW + c) * 4 + ch] = (uint16_t)(pack_bf16(v, 0.f) & 0xffffu);
+        else lds_px[(seg * PXW + c) * 4 + ch] = v;
       }
     }
-    for (int p = tid; p < 3 * PXH * PXW; p += kThreads) lds_px[p * 4 + 3] = 0.f;  // the 4th (zero) channel
+    for (int p = tid; p < 3 * PXH * PXW; p += kThreads) {  // the 4th (zero) channel
+      if constexpr (PXH16) lds_pxh[p * 4 + 3] = 0;
+      else lds_px[p * 4 + 3] = 0.f;
+    }
   };
   // The 9 spatial taps of one stage: every wave multiplies its MB position
   // blocks by the NB output-channel blocks.
@@ -585,6 +594,24 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       const int tap = (st * O::CH + g4 * QE) / 4 + x;
       const int kt = tap / 9, kh = (tap / 3) % 3, kw = tap % 3;
       off[x] = tap < 27 ? ((kt * PXH + kh) * PXW + kw) * 4 : -1;
+    }
+    if constexpr (PXH16) {
+      // this lane's 8 K entries = 2 taps x 4 channels = two 8-byte pixel reads
+      static_assert(TPQ == 2, "bf16: two taps per operand");
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        int i, j;
+        out_local<MODE>(wave, m, l16, &i, &j);
+        const int base = (i * PXW + j) * 4;
+        uint2 p0 = *reinterpret_cast<const uint2*>(&lds_pxh[base + max(off[0], 0)]);
+        uint2 p1 = *reinterpret_cast<const uint2*>(&lds_pxh[base + max(off[1], 0)]);
+        if (off[0] < 0) p0 = make_uint2(0, 0);  // K padding past tap 26
+        if (off[1] < 0) p1 = make_uint2(0, 0);
+        const uint4 aq = make_uint4(p0.x, p0.y, p1.x, p1.y);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
+      }
+      return;
     }
 #pragma unroll
     for (int m = 0; m < MB; ++m) {

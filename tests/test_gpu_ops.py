@@ -62,6 +62,8 @@ CONVS = [
     (0, 64, 3, (2, 5, 20, 72)),
     (1, 64, 128, (2, 5, 20, 72)),
     (1, 128, 128, (2, 5, 20, 72)),
+    (1, 64, 128, (1, 1, 4, 6)),        # one frame: the stride-2 adjoint's frame-0 weight set only
+    (1, 128, 128, (1, 7, 18, 130)),    # 4 coarse frames, ragged row and column tiles of the adjoint
     (2, 128, 128, (2, 3, 10, 36)),
     (2, 128, 64, (2, 3, 10, 36)),
 ]
