@@ -461,6 +461,8 @@ def main():
     ap.add_argument("--coding", type=int, default=1, help="1: time the coding steps on the headline batch")
     ap.add_argument("--select-rate", type=float, default=0.3, help="drop rate of the similarity selection leg")
     ap.add_argument("--residual-theta", type=float, default=0.03, help="residual threshold of the coding leg")
+    ap.add_argument("--serve-clips", type=int, default=48,
+                    help="clips of the serving-loop leg (0 skips it)")
     ap.add_argument("--gemm-ceiling", type=int, default=8192,
                     help="n of the n^3 bf16 library GEMM timed as the part's practical MFMA rate (0 skips it)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -607,6 +609,19 @@ def main():
     if args.fp8_steps > 0:
         fp8 = fp8_leg(tok, synth, wflat, dev, args)
 
+    # ---- serving loop: Poisson arrivals of mixed-resolution clips ------------
+    serving = None
+    if args.serve_clips > 0:
+        from paper_2602_03529_amd import serve
+        try:
+            serving = serve.run(clips=args.serve_clips, rate=40.0, budget_gb=8.0,
+                                log=lambda m: print("bench: serve: " + m, file=sys.stderr, flush=True))
+            serving["workload"] = ("%d clips of 17 frames, Poisson 40 clips/s, resolution uniform over 360p-1080p, "
+                                   "8 GB HBM budget, 4 stream slots, BF16" % args.serve_clips)
+        except Exception as e:  # reported, not fatal: the headline figures above stand on their own
+            serving = dict(error=repr(e))
+        torch.cuda.empty_cache()
+
     # ---- 4 x 17 x 640x480, FP32 and BF16 against the oracle ----------------
     r1 = None
     if args.r1_frames > 0:
@@ -679,7 +694,7 @@ def main():
                 achieved_tflops=round(total_flops / (ms_b / 1e3) / 1e12, 2),
                 conv_layers=conv_layers,
                 roofline=roofline, cpu_baseline=cpu, fp32=fp32, psnr=psnr, r1=r1, train=train, fp8=fp8,
-                coding=coding, mfma_ceiling=ceiling, per_kernel=per_kernel)
+                coding=coding, serving=serving, mfma_ceiling=ceiling, per_kernel=per_kernel)
     print(json.dumps(line), flush=True)
 
 
