@@ -71,6 +71,12 @@ template <> struct Geo<CM_UPF> {
 };
 // The stride-2 adjoint runs on the polyphase path (coarse gradient as source).
 template <> struct Geo<CM_S2T> : Geo<CM_UPF> {};
+// The upsampling adjoint: stride 2 over the fine gradient, 4 x 4 spatial taps
+// (halo columns de-interleaved by parity as for CM_S2), 4 temporal stages.
+template <> struct Geo<CM_UPT> {
+  static constexpr int WR = 1, TW = 32, TH = 4, HH = 2 * TH + 2, HW = 2 * TW + 2;
+  static constexpr int MB = WR * TW / 16, WT = 16, KTS = 4;
+};
 
 // Stride-1 modes give each wave a 4 x 32 sub-tile (waves 2 x 2 over the 8 x 64
 // workgroup tile): an activation operand loaded for halo row r then serves
@@ -103,7 +109,7 @@ __device__ __forceinline__ int act_row(int i, int j, int kh, int kw) {
   using G = Geo<MODE>;
   if constexpr (MODE == CM_S1 || MODE == CM_S1T) {
     return (i + kh) * G::HW + (j + kw);
-  } else if constexpr (MODE == CM_S2) {
+  } else if constexpr (MODE == CM_S2 || MODE == CM_UPT) {
     const int c = 2 * j + kw;
     return (2 * i + kh) * G::HW + (c & 1) * (G::TW + 1) + (c >> 1);
   } else {
@@ -120,7 +126,7 @@ __device__ __forceinline__ void halo_src(int p, int h0, int w0, int* hs, int* ws
   if constexpr (MODE == CM_S1 || MODE == CM_S1T) {
     *hs = h0 - 1 + r;
     *ws = w0 - 1 + pc;
-  } else if constexpr (MODE == CM_S2) {
+  } else if constexpr (MODE == CM_S2 || MODE == CM_UPT) {
     const int c = (pc < G::TW + 1) ? 2 * pc : 2 * (pc - (G::TW + 1)) + 1;
     *hs = 2 * h0 - 1 + r;
     *ws = 2 * w0 - 1 + c;
@@ -272,6 +278,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   if constexpr (MODE == CM_S1T) wset = (size_t)ct * 2 + (tg == 0 ? 1 : 0);
   // stride-2 adjoint: output frame 0 (causal clamp), even, odd output frames
   if constexpr (MODE == CM_S2T) wset = (size_t)ct * 3 + (tg == 0 ? 0 : ((tg & 1) ? 2 : 1));
+  // upsampling adjoint: source frame 0 (causal clamp) vs later frames
+  if constexpr (MODE == CM_UPT) wset = (size_t)ct * 2 + (tg == 0 ? 0 : 1);
   const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + wset * G::KTS * a.in_chunks * WQ;
   const int nstages = G::KTS * a.in_chunks;  // stage = (temporal tap, input chunk)
   // Order of the temporal taps: the blocks of neighbouring output frames run
@@ -293,6 +301,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     else if constexpr (MODE == CM_S2) kt = jt == 2 ? 1 : ((tg & 1) ? 2 * jt : 2 - 2 * jt);
     else if constexpr (MODE == CM_UPF) kt = (tg & 1) ? jt : 1 - jt;
     else if constexpr (MODE == CM_S2T) kt = (tg & 1) ? jt : 1 - jt;  // frame j + 1 shared by 2 j, 2 j + 1 in step 0
+    else if constexpr (MODE == CM_UPT) kt = (tg & 1) ? jt : (jt + 2) & 3;  // fine frames 2 s + 1, 2 s + 2 shared with s + 1
     return kt * a.in_chunks + ck;
   };
 
@@ -309,6 +318,11 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       g = (tg & 1) ? (kt == 0 ? jt + 1 : a.gi0 + a.Ti) : jt + kt;
     }
     else if constexpr (MODE == CM_S2) g = max(2 * tg + kt - 2, 0);
+    else if constexpr (MODE == CM_UPT) {
+      // source frame s reads fine gradient frames 2 s - 1 .. 2 s + 2 (frame -1: none, reported as past the end)
+      g = 2 * tg - 1 + kt;
+      if (g < 0) g = a.gi0 + a.Ti;
+    }
     else {
       // even output frame 2j reads source frames j-1 (clamped) and j; odd 2j+1 reads j and j+1
       const int jt = tg >> 1;
@@ -553,11 +567,12 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       return;
     }
     constexpr int BPR = G::TW / 16;
+    constexpr int KD = MODE == CM_UPT ? 4 : 3;  // spatial taps per dimension
 #pragma unroll 1
-    for (int kh = 0; kh < 3; ++kh) {
+    for (int kh = 0; kh < KD; ++kh) {
 #pragma unroll
-      for (int kw = 0; kw < 3; ++kw) {
-        const int tap = kh * 3 + kw;
+      for (int kw = 0; kw < KD; ++kw) {
+        const int tap = kh * KD + kw;
         uint4 wq[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -985,7 +1000,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   } else {
     for (int j = 0; j < nstages; ++j) {
       const int st = stage_of(j);
-      if constexpr (MODE == CM_S1T || MODE == CM_S2T) {
+      if constexpr (MODE == CM_S1T || MODE == CM_S2T || MODE == CM_UPT) {
         if (src_frame(st / a.in_chunks) >= a.Ti) continue;  // beyond the last gradient frame (uniform per block)
       }
       __syncthreads();
@@ -1260,6 +1275,14 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
     if (a.mode == CM_S1T && a.nt == 16 && !res && !st)
       return launch_one<PREC, CM_S1T, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
     return hipErrorInvalidValue;
+  }
+  if constexpr (PREC == P_F32) {
+    // the upsampling adjoint: 32 output channels a workgroup
+    if (a.mode == CM_UPT) {
+      if (a.nt == 32 && a.out_kind == OUT_ACT && !res && !st)
+        return launch_one<PREC, CM_UPT, 2, IN_ACT, OUT_ACT, false, false>(a, s);
+      return hipErrorInvalidValue;
+    }
   }
   if (a.nt != 64) return hipErrorInvalidValue;
   if (a.mode == CM_S1) {
@@ -1969,6 +1992,9 @@ hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
   // the stride-2 adjoint maps a coarse gradient to its fine-resolution input shape
   if (a.mode == CM_S2T && (a.To != 2 * a.Ti - 1 || a.Ho != 2 * a.Hi || a.Wo != 2 * a.Wi || a.gi0 != 0))
     return hipErrorInvalidValue;
+  // the upsampling adjoint maps a fine gradient to its source shape
+  if (a.mode == CM_UPT && (a.Ti != 2 * a.To - 1 || a.Hi != 2 * a.Ho || a.Wi != 2 * a.Wo || a.gi0 != 0))
+    return hipErrorInvalidValue;
   if (a.prec == P_BF16) return dispatch_prec<P_BF16>(a, s);
   if (a.prec == P_F32) return dispatch_prec<P_F32>(a, s);
   if (a.prec == P_FP8) return dispatch_fp8(a, s);
@@ -2129,6 +2155,32 @@ __device__ float pack_value(const float* __restrict__ w, const PackGeom& g, size
     for (int kt = k0; kt <= k1; ++kt) v += W(ic, oc, kt, kh, kw);
     return v;
   }
+  if (g.mode == CM_UPT) {
+    // [ct][set 2][dt 4][chunk][dh*4+dw][o][quad][QE]
+    const int tap = (int)(e % 16); e /= 16;
+    const int ck = (int)(e % g.chunks); e /= g.chunks;
+    const int dt = (int)(e % 4); e /= 4;
+    const int set = (int)(e % 2); e /= 2;
+    const int ct = (int)e;
+    const int row = tap * g.nt + o;
+    const int q = pq ^ swz(row);
+    const int oc = ct * g.nt + o, ic = ck * g.CH + q * g.QE + x;  // adjoint out / in channels
+    if (oc >= g.Cin || ic >= g.Cout) return 0.f;
+    // forward taps folded onto fine offset d - 1 around 2 s: d = 0 -> 2, 1 -> 1..2, 2 -> 0..1, 3 -> 0
+    auto lo = [](int d) { return d == 0 ? 2 : (d == 1 ? 1 : 0); };
+    auto hi = [](int d) { return d <= 1 ? 2 : (d == 2 ? 1 : 0); };
+    int t0 = lo(dt), t1 = hi(dt);
+    if (set == 0) {  // source frame 0: fine frame dt - 1 collects every tap whose clamped source is 0
+      if (dt == 0) return 0.f;
+      t0 = 0; t1 = 3 - dt;
+    }
+    const int dh = tap >> 2, dw = tap & 3;
+    float v = 0.f;
+    for (int kt = t0; kt <= t1; ++kt)
+      for (int kh = lo(dh); kh <= hi(dh); ++kh)
+        for (int kw = lo(dw); kw <= hi(dw); ++kw) v += W(ic, oc, kt, kh, kw);
+    return v;
+  }
   if (g.mode == CM_I2C) {
     // [ct][chunk][o][quad][QE]: K index k = (kt*9 + kh*3 + kw)*4 + c, zero for c = 3 and past 108
     const int ck = (int)(e % g.chunks); e /= g.chunks;
@@ -2220,15 +2272,16 @@ PackGeom pack_geom(int Cout, int Cin, int prec, int mode, size_t* elems) {
   g.Cout = Cout; g.Cin = Cin; g.mode = mode;
   g.CH = prec == P_BF16 ? 32 : (prec == P_FP8 ? 64 : 16);
   g.QE = g.CH / 4;
-  const bool adj = mode == CM_S1T || mode == CM_S2T;
+  const bool adj = mode == CM_S1T || mode == CM_S2T || mode == CM_UPT;
   const int co = adj ? Cin : Cout;   // the adjoints map Cout channels to Cin channels
   const int ci = adj ? Cout : Cin;
   g.co = co;
-  g.nt = co >= 64 ? 64 : 16;
+  g.nt = mode == CM_UPT ? 32 : (co >= 64 ? 64 : 16);  // the upsampling adjoint: 32 channels a tile (LDS)
   g.chunks = (ci + g.CH - 1) / g.CH;
   if (mode == CM_I2C) g.chunks = kI2cK / g.CH;  // K = 27 taps x 4 channels, padded
   if (mode == CM_UPF) g.R = 2 * 2 * g.chunks * 16;
   else if (mode == CM_S2T) g.R = 3 * 2 * g.chunks * 16;
+  else if (mode == CM_UPT) g.R = 2 * 4 * g.chunks * 16;
   else if (mode == CM_S1T) g.R = 2 * 3 * g.chunks * 9;
   else if (mode == CM_I2C) g.R = g.chunks;
   else g.R = 3 * g.chunks * 9;
@@ -2251,7 +2304,7 @@ hipError_t launch_pack_weights(const float* w, int Cout, int Cin, int prec, int 
   size_t n;
   const PackGeom g = pack_geom(Cout, Cin, prec, mode, &n);
   if (prec == P_FP8) {
-    if (!wscale || mode == CM_S1T || mode == CM_S2T) return hipErrorInvalidValue;
+    if (!wscale || mode == CM_S1T || mode == CM_S2T || mode == CM_UPT) return hipErrorInvalidValue;
     hipLaunchKernelGGL(wscale_kernel, dim3(g.co), dim3(256), 0, s, w, g, g.R, wscale);
     hipLaunchKernelGGL(pack_kernel<P_FP8>, dim3((unsigned)((n / 4 + 255) / 256)), dim3(256), 0, s, w, g, n, dst,
                        (const float*)wscale);

@@ -381,7 +381,7 @@ ModelLayout model_layout(int P) {
       }
       if (L.hasT) {
         L.wpkT[l] = off;
-        off = align256(off + packed_conv_elems(c.cout, c.cin, P, adj_mode(l), &L.ntT[l]) * es);
+        off = align256(off + packed_conv_elems(c.cout, c.cin, P, adj_mode(l, P), &L.ntT[l]) * es);
       }
     } else {
       L.w1T[l] = off;
@@ -401,7 +401,7 @@ tok_status repack(tok_model* m, hipStream_t s) {
     const float* w = m->blob + m->w_off[l];
     if (c.k == 3) {
       if (m->wpk[l]) TOK_HIP(launch_pack_weights(w, c.cout, c.cin, m->prec, conv_mode(l), m->wpk[l], m->wscale[l], s));
-      if (m->wpkT[l]) TOK_HIP(launch_pack_weights(w, c.cout, c.cin, m->prec, adj_mode(l), m->wpkT[l], nullptr, s));
+      if (m->wpkT[l]) TOK_HIP(launch_pack_weights(w, c.cout, c.cin, m->prec, adj_mode(l, m->prec), m->wpkT[l], nullptr, s));
     } else {
       TOK_HIP(launch_transpose(w, c.cout, c.cin, m->w1x1T[l], s));
     }

@@ -32,7 +32,12 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 // 2 x 2 x 2 source offsets per output; along each of t, h, w an output of
 // parity 0 takes tap 1 from offset 0, parity 1 taps 2 and 0 from offsets 0
 // and +1), instead of zero insertion and the dense stride-1 adjoint.
-enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3, CM_S1T = 4, CM_I2C = 5, CM_S2T = 6 };
+// CM_UPT: the adjoint of the upsampling conv, fine gradient in, source-resolution
+// gradient out: a stride-2 conv over the fine gradient with 4 x 4 x 4 folded
+// taps (along each dimension fine offsets -1, 0, +1, +2 around 2 s carry
+// forward taps 2, 1 + 2, 0 + 1, 0; source frame 0 also collects the causal
+// clamp), 8 instead of 27 Cin Cout MACs per fine position.
+enum ConvMode { CM_S1 = 0, CM_S2 = 1, CM_UP = 2, CM_UPF = 3, CM_S1T = 4, CM_I2C = 5, CM_S2T = 6, CM_UPT = 7 };
 constexpr int kI2cK = 128;  // 27 taps x 4 channels, padded to whole 32-element bf16 chunks
 enum InKind { IN_ACT = 0, IN_U8 = 1 };
 // OUT_ACT: chunked activations of the kernel's output precision (bf16 for
@@ -120,7 +125,7 @@ struct ConvLaunch {
 
 // Tile geometry per mode (output rows x cols per workgroup).
 inline void conv_tile(int mode, int* th, int* tw) {
-  if (mode == CM_S2) { *th = 4; *tw = 32; }
+  if (mode == CM_S2 || mode == CM_UPT) { *th = 4; *tw = 32; }
   else { *th = 8; *tw = 64; }
 }
 

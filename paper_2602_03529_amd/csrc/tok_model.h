@@ -54,8 +54,15 @@ inline int conv_mode(int l) {
   return CM_S1;
 }
 
-// Mode of each 3x3x3 layer's input-gradient conv (the packed adjoint kernel).
-inline int adj_mode(int l) { return conv_mode(l) == CM_S2 ? CM_S2T : CM_S1T; }
+// Mode of each 3x3x3 layer's input-gradient conv (the packed adjoint kernel):
+// polyphase for the strided layers, and for the upsampling layers in fp32
+// (in bf16 the dense adjoint at the fine resolution is faster: the polyphase
+// form stages twice the bytes per output of the strided forward conv).
+inline int adj_mode(int l, int prec) {
+  if (conv_mode(l) == CM_S2) return CM_S2T;
+  if (conv_mode(l) == CM_UPF && prec == P_F32) return CM_UPT;
+  return CM_S1T;
+}
 
 constexpr float kGnEps = 1e-6f;
 constexpr float kCommitWeight = 0.1f;

@@ -55,6 +55,12 @@ int fwd_mode(int view, int Cin) {
   return view == 1 ? CM_S2 : CM_UPF;
 }
 int wgrad_view_mode(int view) { return view == 0 ? CM_S1 : (view == 1 ? CM_S2 : CM_UP); }
+// input-gradient conv of a view: polyphase for stride 2, and for the upsampling view in fp32
+int adj_op_mode(int P, int view) {
+  if (view == 1) return CM_S2T;
+  if (view == 2 && P == P_F32) return CM_UPT;
+  return CM_S1T;
+}
 
 ConvOpWs conv_op_ws(int P, int view, int N, int Ti, int Hi, int Wi, int Cin, int Cout) {
   int To, Ho, Wo;
@@ -62,7 +68,7 @@ ConvOpWs conv_op_ws(int P, int view, int N, int Ti, int Hi, int Wi, int Cin, int
   ConvOpWs w{};
   const size_t es = elem_bytes(P);
   const size_t pf = packed_conv_elems(Cout, Cin, P, fwd_mode(view, Cin), &w.nt);
-  const size_t pa = packed_conv_elems(Cout, Cin, P, view == 1 ? CM_S2T : CM_S1T, &w.ntT);
+  const size_t pa = packed_conv_elems(Cout, Cin, P, adj_op_mode(P, view), &w.ntT);
   w.pk = align256(std::max(pf, pa) * es);
   w.zeros = align256((size_t)std::max(Cin, Cout) * 4);
   const size_t tiles = (size_t)cdiv(Ho, 8) * cdiv(Wo, 64);
@@ -213,7 +219,7 @@ tok_status tok_op_conv3d_dgrad(tok_precision prec, int view, const void* dy, int
   TOK_TRY(conv_op_check(prec, view, N, Ti, Hi, Wi, Cin, Cout, ws, ws_bytes, &a));
   if ((Cout != 3 && !al16(dy)) || (Cin != 3 && !al16(dx))) return fail(TOK_EINVAL, "activations must be 16-byte aligned");
   const int CH = chan_chunk(a.P);
-  TOK_HIP(launch_pack_weights(w, Cout, Cin, a.P, view == 1 ? CM_S2T : CM_S1T, ws_pk(a), nullptr, s));
+  TOK_HIP(launch_pack_weights(w, Cout, Cin, a.P, adj_op_mode(a.P, view), ws_pk(a), nullptr, s));
   TOK_HIP(launch_fill_zero(ws_zeros(a), (size_t)Cin, s));
   const int out_kind = Cin == 3 ? OUT_RGB32 : OUT_ACT;
   const void* g = dy;
@@ -228,6 +234,10 @@ tok_status tok_op_conv3d_dgrad(tok_precision prec, int view, const void* dy, int
   } else if (view == 1) {
     // stride 2: the polyphase adjoint, coarse gradient in, fine gradient out
     TOK_HIP(run_conv(a, CM_S2T, ws_pk(a), ws_zeros(a), a.w.ntT, Cout, Cin, g, IN_ACT, a.To, a.Ho, a.Wo, dx, OUT_ACT,
+                     Ti, Hi, Wi, nullptr, nullptr, s));
+  } else if (adj_op_mode(a.P, view) == CM_UPT) {
+    // upsampling view, fp32: the polyphase adjoint, fine gradient in, source gradient out
+    TOK_HIP(run_conv(a, CM_UPT, ws_pk(a), ws_zeros(a), a.w.ntT, Cout, Cin, g, IN_ACT, a.To, a.Ho, a.Wo, dx, OUT_ACT,
                      Ti, Hi, Wi, nullptr, nullptr, s));
   } else {
     // upsample then stride-1 conv: the stride-1 adjoint at the fine resolution, then the upsample adjoint

@@ -175,6 +175,14 @@ tok_status adj_s2(const TrainCtx& c, int l, const void* gy, int Tc, int Hc, int 
                Wc, gx, OUT_ACT, 2 * Tc - 1, 2 * Hc, 2 * Wc, nullptr, nullptr);
 }
 
+// Input gradient of layer l's upsampling conv in polyphase form (fp32 models):
+// fine gradient (Tf, Hf, Wf) in, source gradient ((Tf + 1) / 2, Hf / 2, Wf / 2) out.
+tok_status adj_up(const TrainCtx& c, int l, const void* gy, int Tf, int Hf, int Wf, void* gx) {
+  const tok_model* m = c.m;
+  return tconv(c, K_DGRAD, CM_UPT, m->wpkT[l], m->zeros, m->ntT[l], kConv[l].cout, kConv[l].cin, gy, IN_ACT, Tf, Hf,
+               Wf, gx, OUT_ACT, (Tf + 1) / 2, Hf / 2, Wf / 2, nullptr, nullptr);
+}
+
 tok_status wgrad(const TrainCtx& c, int l, int view, const void* x, int Ti, int Hi, int Wi, const void* dy, int To,
                  int Ho, int Wo, float* dweights) {
   const ConvSpec& cs = kConv[l];
@@ -386,17 +394,24 @@ tok_status backward_impl(tok_model* m, const uint8_t* x, int N, int T, int H, in
   TOK_TRY(rb_backward(c, L_D_RB1_A, N_D_RB1_A, c.at(p.U1), dweights));
   // up1: conv on the upsampled level-1 activations
   TOK_TRY(wgrad(c, L_UP1, CM_UP, c.at(p.U2), d.T1, d.H1, d.W1, GB, T, H, W, dweights));
-  TOK_TRY(adj(c, L_UP1, GB, T, H, W, WIDE, OUT_ACT));
-  {
+  if (adj_mode(L_UP1, m->prec) == CM_UPT) {
+    TOK_TRY(adj_up(c, L_UP1, GB, T, H, W, c.at(p.G1a)));
+  } else {
+    TOK_TRY(adj(c, L_UP1, GB, T, H, W, WIDE, OUT_ACT));
     Timed tm(m, K_BWD_MISC, s);
     TOK_HIP(launch_up_adjoint(WIDE, c.at(p.G1a), N, d.T1, d.H1, d.W1, wide_chunks, m->prec, s));
   }
   // up2
   TOK_TRY(wgrad(c, L_UP2, CM_UP, c.at(p.P), d.T2, d.H2, d.W2, c.at(p.G1a), d.T1, d.H1, d.W1, dweights));
-  TOK_TRY(adj(c, L_UP2, c.at(p.G1a), d.T1, d.H1, d.W1, c.at(p.G1b), OUT_ACT));
-  {
+  if (adj_mode(L_UP2, m->prec) == CM_UPT) {
+    TOK_TRY(adj_up(c, L_UP2, c.at(p.G1a), d.T1, d.H1, d.W1, c.at(p.G2a)));
+  } else {
+    TOK_TRY(adj(c, L_UP2, c.at(p.G1a), d.T1, d.H1, d.W1, c.at(p.G1b), OUT_ACT));
     Timed tm(m, K_BWD_MISC, s);
     TOK_HIP(launch_up_adjoint(c.at(p.G1b), c.at(p.G2a), N, d.T2, d.H2, d.W2, wide_chunks, m->prec, s));
+  }
+  {
+    Timed tm(m, K_BWD_MISC, s);
     // proj_in (6 -> 128), FSQ straight-through + commitment, proj (128 -> 6)
     const int HW2 = d.H2 * d.W2;
     TOK_HIP(launch_outer6(c.at<float>(p.DEC), c.at(p.G2a), p.ntok, HW2, m->prec, c.at<float>(p.O6P), 1,

@@ -66,6 +66,7 @@ CONVS = [
     (1, 128, 128, (1, 7, 18, 130)),    # 4 coarse frames, ragged row and column tiles of the adjoint
     (2, 128, 128, (2, 3, 10, 36)),
     (2, 128, 64, (2, 3, 10, 36)),
+    (2, 128, 64, (1, 2, 5, 33)),       # odd source height, ragged tiles of the upsampling adjoint
 ]
 
 
