@@ -75,7 +75,7 @@ ConvOpWs conv_op_ws(int P, int view, int N, int Ti, int Hi, int Wi, int Cin, int
   w.stats = Cin == 3 ? align256((size_t)N * To * tiles * 32 * sizeof(float4)) : 0;
   // fine-resolution temporaries of the adjoints and one-chunk copies of 3-channel operands
   size_t tmp = 0;
-  if (view == 2) tmp = (size_t)N * To * Ho * Wo * cdiv(Cin, chan_chunk(P)) * kChunkBytes;
+  if (view == 2 && adj_op_mode(P, view) == CM_S1T) tmp = (size_t)N * To * Ho * Wo * cdiv(Cin, chan_chunk(P)) * kChunkBytes;
   if (Cout == 3) tmp = (size_t)N * To * Ho * Wo * kChunkBytes;
   if (Cin == 3) tmp = (size_t)N * Ti * Hi * Wi * kChunkBytes;
   w.tmp = align256(tmp);
