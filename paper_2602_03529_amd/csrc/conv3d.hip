@@ -1260,6 +1260,230 @@ hipError_t launch_one(const ConvLaunch& a, hipStream_t s) {
 }
 
 
+// ---------------------------------------------------------------------------
+// 64 -> 3 last layer (bf16 or MX-fp8 input), walking the frames of one
+// spatial tile.  The workgroup owns an 8 x 64 output tile of one clip and
+// stages every input frame's halo once (per 64-byte channel chunk), instead of
+// once per temporal tap.  The MFMA rows are (colour c, temporal tap kt)
+// pairs, row 4 c + kt (12 of 16 used), so for output position p of a wave's
+// block the lane (l16 = p, g4 = c) receives
+//   d[kt] = sum_{kh, kw, i} W[c, i, kt, kh, kw] x[i, f, p + (kh, kw)]
+// for the frame f being staged; output frame t gathers d[0] of frame t - 2,
+// d[1] of t - 1 and d[2] of t (causal clamp: frame 0 supplies every tap that
+// would read before it).  Each lane keeps the three output frames still
+// collecting taps in registers and stores a frame once its last tap is in.
+// Per output frame the sum is d[0] + d[1] + d[2] in that order (bf16: on top
+// of the bias; fp8: then scaled by the colour's weight scale and biased), on
+// every frame window, so chunked and whole-clip decodes agree bit for bit.
+// Wave w owns output rows 2 w, 2 w + 1 (8 blocks of 16 positions).
+// bf16: K = 32 channels x one tap per MFMA (16x16x32).  fp8: K = 128 = two
+// taps x 64 channels per MFMA (16x16x128 with the activations' E8M0 scales),
+// taps paired as in the fp8 stride-1 conv (a tenth, zero-weight tap pads the
+// last pair).
+// ---------------------------------------------------------------------------
+constexpr int kWalkHW = 66, kWalkHalo = 10 * kWalkHW, kWalkHQ = kWalkHalo * 4;
+
+template <int PREC>
+__global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a) {
+  constexpr bool F8 = PREC == P_FP8;
+  constexpr int NCK = F8 ? 1 : 2;  // input chunks (64 channels)
+  __shared__ uint4 lds_h[kWalkHQ];
+  __shared__ uint16_t lds_sc[F8 ? kWalkHalo : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  int v = xcd_remap(blockIdx.x, gridDim.x);
+  const int tw = v % a.tiles_w; v /= a.tiles_w;
+  const int th = v % a.tiles_h; v /= a.tiles_h;
+  const int n = v;
+  const int h0 = th * 8, w0 = tw * 64;
+
+  // this lane's weight operands: row l16 = (c, kt) of the packed stride-1
+  // layout's 16-row tile [kt][chunk][tap][row c][quad ^ swz(16 tap + c)]
+  const int wc = l16 >> 2, wkt = l16 & 3;
+  const bool wrow = wc < 3 && wkt < 3;
+  const uint4* wq = reinterpret_cast<const uint4*>(a.wpk);
+  // the 81 used weight rows (kt, tap, c) of each chunk in LDS, compact row
+  // (kt * 9 + tap) * 3 + c, each row's quads in their packed (swizzled) order
+  __shared__ uint4 lds_w[NCK * 81 * 4];
+  for (int e = tid; e < NCK * 81 * 4; e += kThreads) {
+    const int ck = e / (81 * 4), r = (e >> 2) % 81, c = r % 3, kt = r / 27, tap = (r / 3) % 9;
+    lds_w[e] = ck < a.in_chunks ? wq[((size_t)((kt * a.in_chunks + ck) * 9 + tap) * 16 + c) * 4 + (e & 3)]
+                                : make_uint4(0, 0, 0, 0);
+  }
+  // LDS index of this lane's quad q of (chunk ck, tap): row (c, kt) = (wc, wkt)
+  auto wslot = [&](int ck, int tap, int q) {
+    return (ck * 81 + (wkt * 9 + tap) * 3 + wc) * 4 + (q ^ swz(tap * 16 + wc));
+  };
+  const float bias = g4 < 3 ? a.bias[g4] : 0.f;
+  const float wsc = F8 && g4 < 3 ? a.wscale[g4] : 1.f;
+
+  // halo slots this thread fills (the same in every stage): in-frame quad offset or -1
+  constexpr int NHS = (kWalkHQ + kThreads - 1) / kThreads;
+  int hoff[NHS];
+#pragma unroll
+  for (int k = 0; k < NHS; ++k) {
+    const int e = wave * 64 + k * kThreads + lane;
+    hoff[k] = -1;
+    if (e < kWalkHQ) {
+      const int p = e >> 2, q = (e & 3) ^ swz(p);
+      const int hs = h0 - 1 + p / kWalkHW, ws = w0 - 1 + p % kWalkHW;
+      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) hoff[k] = (hs * a.Wi + ws) * 4 + q;
+    }
+  }
+  // fp8: in-frame position of halo rows tid, tid + 256, tid + 512 (-1 outside)
+  constexpr int NSR = F8 ? (kWalkHalo + kThreads - 1) / kThreads : 1;
+  int soff[NSR];
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) {
+    const int p = tid + k * kThreads;
+    const int hs = h0 - 1 + p / kWalkHW, ws = w0 - 1 + p % kWalkHW;
+    soff[k] = (F8 && p < kWalkHalo && hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) ? hs * a.Wi + ws : -1;
+  }
+  const size_t plane_in = (size_t)a.Hi * a.Wi, plane_out = (size_t)a.Ho * a.Wo;
+
+  // output frames t, t + 1, t + 2 still collecting taps (colour g4, 8 positions)
+  const float init = F8 ? 0.f : bias;
+  float o0[8], o1[8], o2[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) o0[m] = o1[m] = o2[m] = init;
+
+  const int f_first = max(a.go0 - 2, 0), f_end = a.go0 + a.To;
+  for (int fg = f_first; fg < f_end; ++fg) {
+    f32x4 d[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) d[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ck = 0; ck < NCK; ++ck) {
+      if (ck >= a.in_chunks) break;
+      __syncthreads();  // every wave is done reading the previous stage
+      const size_t fplane = ((size_t)n * a.Ti + (fg - a.gi0)) * a.in_chunks + ck;
+      const uint4* src = reinterpret_cast<const uint4*>(a.in) + fplane * plane_in * 4;
+      uint16_t sv[NSR];
+      if constexpr (F8) {
+        // scale bytes of the halo rows (outside the frame: zeros with scale 2^0)
+        const uint16_t* ssrc = reinterpret_cast<const uint16_t*>(a.in_scale) + fplane * plane_in;
+#pragma unroll
+        for (int k = 0; k < NSR; ++k) sv[k] = soff[k] >= 0 ? ssrc[soff[k]] : (uint16_t)0x7F7F;
+      }
+#pragma unroll
+      for (int k = 0; k < NHS; ++k) {
+        const int base = wave * 64 + k * kThreads, e = base + lane;
+        if (e < kWalkHQ) {
+          if (hoff[k] >= 0) lds_dma16(src + hoff[k], &lds_h[base]);
+          else lds_h[e] = make_uint4(0, 0, 0, 0);
+        }
+      }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if constexpr (F8) {
+#pragma unroll
+        for (int k = 0; k < NSR; ++k)
+          if (tid + k * kThreads < kWalkHalo) lds_sc[tid + k * kThreads] = sv[k];
+      }
+      __syncthreads();
+      if constexpr (F8) {
+        // pair t: data of tap 2 t + (g4 >> 1) (quads h, 2 + h), scale of tap
+        // 2 t + h, 32-channel block g4 >> 1 (tap 9 stands for tap 8)
+        const int h = g4 & 1, sblk = g4 >> 1;
+#pragma unroll 1
+        for (int t = 0; t < 5; ++t) {
+          const int tap = min(2 * t + (g4 >> 1), 8), stap = min(2 * t + h, 8);
+          const int kh = tap / 3, kw = tap % 3, skh = stap / 3, skw = stap % 3;
+          // weights of row (c, kt) = (wc, wkt), tap 2 t + (g4 >> 1); zero for the unused rows and the tenth tap
+          i32x8 wv = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+          if (wrow && 2 * t + (g4 >> 1) < 9) {
+            const uint4 q0 = lds_w[wslot(0, tap, h)], q1 = lds_w[wslot(0, tap, 2 + h)];
+            wv = i32x8{(int)q0.x, (int)q0.y, (int)q0.z, (int)q0.w, (int)q1.x, (int)q1.y, (int)q1.z, (int)q1.w};
+          }
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const int i = 2 * wave + (m >> 2), j = (m & 3) * 16 + l16;
+            const i32x8 aq = ld_fp8_pair(lds_h, (i + kh) * kWalkHW + j + kw, h);
+            const int sb = (lds_sc[(i + skh) * kWalkHW + j + skw] >> (8 * sblk)) & 255;
+            mfma_fp8(d[m], wv, aq, sb);
+          }
+        }
+      } else {
+        // halo row 2 w + hr serves output row r = hr - kh for kh = 0..2
+#pragma unroll 1
+        for (int hr = 0; hr < 4; ++hr)
+#pragma unroll
+          for (int kw = 0; kw < 3; ++kw) {
+            uint4 bq[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              const int p = (2 * wave + hr) * kWalkHW + cb * 16 + l16 + kw;
+              bq[cb] = lds_h[p * 4 + (g4 ^ swz(p))];
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+              const int kh = hr - r;
+              if (kh < 0 || kh > 2) continue;
+              uint4 wv = make_uint4(0, 0, 0, 0);
+              if (wrow) wv = lds_w[wslot(ck, kh * 3 + kw, g4)];
+#pragma unroll
+              for (int cb = 0; cb < 4; ++cb)
+                d[r * 4 + cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, wv), __builtin_bit_cast(bf16x8, bq[cb]), d[r * 4 + cb], 0, 0, 0);
+            }
+          }
+      }
+    }
+    // taps of frame fg: d[m][kt] belongs to output frame fg + 2 - kt (frame 0: to
+    // every output frame whose clamped tap reads it)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (fg == 0) {
+        o0[m] = ((o0[m] + d[m][0]) + d[m][1]) + d[m][2];
+        o1[m] = (o1[m] + d[m][0]) + d[m][1];
+        o2[m] = o2[m] + d[m][0];
+      } else {
+        o0[m] += d[m][2];
+        o1[m] += d[m][1];
+        o2[m] += d[m][0];
+      }
+    }
+    // output frame fg is complete
+    if (fg >= a.go0 && g4 < 3) {
+      const int to = fg - a.go0;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int oh = h0 + 2 * wave + (m >> 2), ow = w0 + (m & 3) * 16 + l16;
+        if (oh >= a.Ho || ow >= a.Wo) continue;
+        float y = F8 ? o0[m] * wsc + bias : o0[m];
+        if (a.blend_prev != nullptr && fg < a.blend_n) {
+          // frame i = fg + 1 of the GoP: a_i prev[Tp - n + i] + (1 - a_i) x_hat, a_i = (n - i) / n
+          const float al = (float)(a.blend_n - (fg + 1)) / (float)a.blend_n, be = 1.0f - al;
+          const float pv = a.blend_prev[(((size_t)n * a.blend_Tp + (a.blend_Tp - a.blend_n + fg)) * plane_out +
+                                         (size_t)oh * a.Wo + ow) * 3 + g4];
+          y = al * pv + be * y;
+        }
+        reinterpret_cast<float*>(a.out)[(((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3 +
+                                        g4] = y;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      o0[m] = o1[m];
+      o1[m] = o2[m];
+      o2[m] = init;
+    }
+  }
+}
+
+// Launches the frame-walking last layer after checking what it assumes: 3
+// output colours in one 16-row tile, at most 64 input channels, and every
+// walked input frame (max(go0 - 2, 0) .. go0 + To - 1) inside the input buffer.
+template <int PREC>
+hipError_t launch_rgb_walk(const ConvLaunch& a, hipStream_t s) {
+  if (a.Cout != 3 || a.nt != 16 || a.in_chunks > (PREC == P_FP8 ? 1 : 2) || a.gi0 > (a.go0 > 2 ? a.go0 - 2 : 0) ||
+      a.go0 + a.To - a.gi0 > a.Ti)
+    return hipErrorInvalidValue;
+  const long long nb = (long long)a.N * a.tiles_h * a.tiles_w;
+  if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(conv_rgb_walk_kernel<PREC>, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   // The configurations the tokenizer uses.
@@ -1270,8 +1494,10 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
     return hipErrorInvalidValue;
   }
   if (a.out_kind == OUT_RGB32) {
-    if (a.mode == CM_S1 && a.nt == 16 && !res && !st)
+    if (a.mode == CM_S1 && a.nt == 16 && !res && !st) {
+      if constexpr (PREC == P_BF16) return launch_rgb_walk<P_BF16>(a, s);
       return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
+    }
     if (a.mode == CM_S1T && a.nt == 16 && !res && !st)
       return launch_one<PREC, CM_S1T, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
     return hipErrorInvalidValue;
@@ -1955,8 +2181,7 @@ hipError_t dispatch_fp8(const ConvLaunch& a, hipStream_t s) {
   const bool res = a.resid != nullptr, st = a.stats != nullptr;
   if (a.in_kind != IN_ACT || !a.in_scale || !a.wscale) return hipErrorInvalidValue;
   if (a.out_kind == OUT_RGB32) {
-    if (a.mode == CM_S1 && a.nt == 16 && !res && !st)
-      return launch_one<P_FP8, CM_S1, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
+    if (a.mode == CM_S1 && a.nt == 16 && !res && !st) return launch_rgb_walk<P_FP8>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.nt != 64 || a.Cout % 64 != 0) return hipErrorInvalidValue;

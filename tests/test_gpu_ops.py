@@ -60,6 +60,7 @@ CONVS = [
     (0, 128, 64, (2, 3, 20, 72)),
     (0, 3, 64, (2, 5, 20, 72)),
     (0, 64, 3, (2, 5, 20, 72)),
+    (0, 64, 3, (1, 9, 17, 130)),       # last layer: nine frames walked, ragged row and column tiles
     (1, 64, 128, (2, 5, 20, 72)),
     (1, 128, 128, (2, 5, 20, 72)),
     (1, 64, 128, (1, 1, 4, 6)),        # one frame: the stride-2 adjoint's frame-0 weight set only
