@@ -50,9 +50,12 @@ template <> struct Geo<CM_S1> {
   static constexpr int WR = 2, TW = 64, TH = 8, HH = TH + 2, HW = TW + 2;
   static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
 };
+// Stride 2: a stage is one kernel row kh of one (temporal tap, input chunk):
+// the 8 input rows 2 i + kh - 1 the tile's output rows i read through it,
+// columns de-interleaved by parity, and that row's 3 taps of weights.
 template <> struct Geo<CM_S2> {
-  static constexpr int WR = 1, TW = 32, TH = 4, HH = 2 * TH + 1, HW = 2 * TW + 1;
-  static constexpr int MB = WR * TW / 16, WT = 9, KTS = 3;
+  static constexpr int WR = 2, TW = 32, TH = 8, HH = TH, HW = 2 * TW + 1;
+  static constexpr int MB = WR * TW / 16, WT = 3, KTS = 3;
 };
 template <> struct Geo<CM_S1T> : Geo<CM_S1> {};
 // im2col first layer: no halo staging (the MFMA operands are gathered from
@@ -128,7 +131,7 @@ __device__ __forceinline__ void halo_src(int p, int h0, int w0, int* hs, int* ws
     *ws = w0 - 1 + pc;
   } else if constexpr (MODE == CM_S2 || MODE == CM_UPT) {
     const int c = (pc < G::TW + 1) ? 2 * pc : 2 * (pc - (G::TW + 1)) + 1;
-    *hs = 2 * h0 - 1 + r;
+    *hs = MODE == CM_S2 ? 2 * (h0 + r) - 1 : 2 * h0 - 1 + r;  // stride 2: row of kernel row 0
     *ws = 2 * w0 - 1 + c;
   } else {  // CM_UPF / CM_S2T: source rows / columns of the tile
     *hs = (h0 >> 1) - 1 + r;
@@ -281,7 +284,9 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   // upsampling adjoint: source frame 0 (causal clamp) vs later frames
   if constexpr (MODE == CM_UPT) wset = (size_t)ct * 2 + (tg == 0 ? 0 : 1);
   const uint4* wbase = reinterpret_cast<const uint4*>(a.wpk) + wset * G::KTS * a.in_chunks * WQ;
-  const int nstages = G::KTS * a.in_chunks;  // stage = (temporal tap, input chunk)
+  constexpr int KHS = MODE == CM_S2 ? 3 : 1;  // stride 2: one stage per kernel row
+  const int spk = a.in_chunks * KHS;          // stages per temporal tap
+  const int nstages = G::KTS * spk;           // stage = (temporal tap, input chunk[, kernel row])
   // Order of the temporal taps: the blocks of neighbouring output frames run
   // side by side (output frame is the fastest tile index after the channel
   // tile), so each block takes its taps in an order in which neighbours read
@@ -294,7 +299,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   // depends on the global output frame only, so chunked and whole-clip runs
   // still sum in the same order.
   auto stage_of = [&](int j) {
-    const int jt = j / a.in_chunks, ck = j - jt * a.in_chunks;
+    const int jt = j / spk, ck = j - jt * spk;  // (ck: chunk and kernel row)
     int kt = jt;
     if constexpr (MODE == CM_S1) kt = (jt + 5 - tg % 3) % 3;
     else if constexpr (MODE == CM_S1T) kt = (jt + 3 - tg % 3) % 3;
@@ -302,7 +307,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     else if constexpr (MODE == CM_UPF) kt = (tg & 1) ? jt : 1 - jt;
     else if constexpr (MODE == CM_S2T) kt = (tg & 1) ? jt : 1 - jt;  // frame j + 1 shared by 2 j, 2 j + 1 in step 0
     else if constexpr (MODE == CM_UPT) kt = (tg & 1) ? jt : (jt + 2) & 3;  // fine frames 2 s + 1, 2 s + 2 shared with s + 1
-    return kt * a.in_chunks + ck;
+    return kt * spk + ck;
   };
 
   // Input buffer frame read by temporal tap kt (causal in global frame
@@ -333,18 +338,30 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
 
   // Halo slots this thread's lanes fill are the same in every stage: keep
   // their in-frame quad offsets (or -1 for the zero padding) in registers.
+  // Stride 2: the offset for kernel row 0 (kernel row kh reads kh rows
+  // further down) and a mask of the kernel rows whose source row is inside
+  // the frame.
   constexpr int NHS = (HQ + kThreads - 1) / kThreads;
   int hoff[NHS];
+  int hmask[MODE == CM_S2 ? NHS : 1];
 #pragma unroll
   for (int k = 0; k < NHS; ++k) {
     const int e = wave * 64 + k * kThreads + lane;
     hoff[k] = -1;
+    if constexpr (MODE == CM_S2) hmask[k] = 0;
     if (e < HQ) {
       const int p = e >> 2;
       const int q = (e & 3) ^ swz(p);
       int hs, ws;
       halo_src<MODE>(p, h0, w0, &hs, &ws);
-      if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) hoff[k] = (hs * a.Wi + ws) * 4 + q;
+      if constexpr (MODE == CM_S2) {
+        hoff[k] = (hs * a.Wi + ws) * 4 + q;
+#pragma unroll
+        for (int kh = 0; kh < 3; ++kh)
+          if (hs + kh >= 0 && hs + kh < a.Hi && ws >= 0 && ws < a.Wi) hmask[k] |= 1 << kh;
+      } else if (hs >= 0 && hs < a.Hi && ws >= 0 && ws < a.Wi) {
+        hoff[k] = (hs * a.Wi + ws) * 4 + q;
+      }
     }
   }
   // fp8: in-frame position of halo rows tid, tid + 256, ... (scale staging), -1 outside
@@ -367,7 +384,9 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
   // the halo holds logical quad pq ^ swz(p) of halo row p; rows outside the
   // frame are written as zeros (the conv's zero padding).
   auto issue_async = [&](int st, int buf) {
-    const int kt = st / a.in_chunks, ck = st - kt * a.in_chunks;
+    // stage st = (kt, chunk ck[, kernel row kh]); its weights follow the
+    // previous stage's in the packed layout (stride 2: a kernel row's 3 taps)
+    const int kt = st / spk, ck = (st - kt * spk) / KHS, kh = st % KHS;
     const uint4* wsrc = wbase + (size_t)st * WQ;
     if constexpr (RGBL) {
       // compact: row 3 tap + c of LDS <- packed row 16 tap + c (quads as packed, i.e. swizzled by the packed row)
@@ -387,8 +406,13 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       const int base = wave * 64 + k * kThreads;
       const int e = base + lane;
       if (e < HQ) {
-        if (hoff[k] >= 0) lds_dma16(src + hoff[k], &lds_a[buf][base]);
-        else lds_a[buf][e] = make_uint4(0, 0, 0, 0);
+        if constexpr (MODE == CM_S2) {
+          if ((hmask[k] >> kh) & 1) lds_dma16(src + hoff[k] + kh * a.Wi * 4, &lds_a[buf][base]);
+          else lds_a[buf][e] = make_uint4(0, 0, 0, 0);
+        } else {
+          if (hoff[k] >= 0) lds_dma16(src + hoff[k], &lds_a[buf][base]);
+          else lds_a[buf][e] = make_uint4(0, 0, 0, 0);
+        }
       }
     }
     if constexpr (F8) {
@@ -567,6 +591,28 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       return;
     }
     constexpr int BPR = G::TW / 16;
+    if constexpr (MODE == CM_S2) {
+      // the stage's kernel row: halo row i serves output row i, column 2 j + kw
+#pragma unroll
+      for (int kw = 0; kw < 3; ++kw) {
+        uint4 wq[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int row = kw * NT + b * 16 + l16;
+          wq[b] = lds_w[buf][row * 4 + (g4 ^ swz(row))];
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const int i = wave * G::WR + m / BPR;
+          const int c = 2 * ((m % BPR) * 16 + l16) + kw;
+          const int row = i * G::HW + (c & 1) * (G::TW + 1) + (c >> 1);
+          const uint4 aq = lds_a[buf][row * 4 + (g4 ^ swz(row))];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) mfma_quad<PREC>(acc[m][b], wq[b], aq);
+        }
+      }
+      return;
+    }
     constexpr int KD = MODE == CM_UPT ? 4 : 3;  // spatial taps per dimension
 #pragma unroll 1
     for (int kh = 0; kh < KD; ++kh) {
@@ -1510,16 +1556,17 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
       return hipErrorInvalidValue;
     }
   }
+  if (a.mode == CM_S2) {
+    if (!res && !st && a.nt == 128) return launch_one<PREC, CM_S2, 8, IN_ACT, OUT_ACT, false, false>(a, s);
+    if (!res && !st && a.nt == 64) return launch_one<PREC, CM_S2, 4, IN_ACT, OUT_ACT, false, false>(a, s);
+    return hipErrorInvalidValue;
+  }
   if (a.nt != 64) return hipErrorInvalidValue;
   if (a.mode == CM_S1) {
     if (!res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, true>(a, s);
     if (res && st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, true>(a, s);
     if (res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, true, false>(a, s);
     if (!res && !st) return launch_one<PREC, CM_S1, 4, IN_ACT, OUT_ACT, false, false>(a, s);
-    return hipErrorInvalidValue;
-  }
-  if (a.mode == CM_S2) {
-    if (!res && !st) return launch_one<PREC, CM_S2, 4, IN_ACT, OUT_ACT, false, false>(a, s);
     return hipErrorInvalidValue;
   }
   if (a.mode == CM_S1T) {
@@ -2501,7 +2548,9 @@ PackGeom pack_geom(int Cout, int Cin, int prec, int mode, size_t* elems) {
   const int co = adj ? Cin : Cout;   // the adjoints map Cout channels to Cin channels
   const int ci = adj ? Cout : Cin;
   g.co = co;
-  g.nt = mode == CM_UPT ? 32 : (co >= 64 ? 64 : 16);  // the upsampling adjoint: 32 channels a tile (LDS)
+  // the upsampling adjoint: 32 channels a tile (LDS); stride 2: 128 when they
+  // come in whole tiles (its stages are one kernel row, so 128 fit in LDS)
+  g.nt = mode == CM_UPT ? 32 : (mode == CM_S2 && co % 128 == 0 ? 128 : (co >= 64 ? 64 : 16));
   g.chunks = (ci + g.CH - 1) / g.CH;
   if (mode == CM_I2C) g.chunks = kI2cK / g.CH;  // K = 27 taps x 4 channels, padded
   if (mode == CM_UPF) g.R = 2 * 2 * g.chunks * 16;

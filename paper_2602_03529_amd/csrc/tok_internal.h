@@ -125,7 +125,8 @@ struct ConvLaunch {
 
 // Tile geometry per mode (output rows x cols per workgroup).
 inline void conv_tile(int mode, int* th, int* tw) {
-  if (mode == CM_S2 || mode == CM_UPT) { *th = 4; *tw = 32; }
+  if (mode == CM_S2) { *th = 8; *tw = 32; }
+  else if (mode == CM_UPT) { *th = 4; *tw = 32; }
   else { *th = 8; *tw = 64; }
 }
 
