@@ -313,8 +313,17 @@ const char* tok_kernel_name(int k);
 tok_status tok_model_set_weights(tok_model* model, const float* weights, hipStream_t stream);
 
 /* Bytes of workspace for tok_train_forward + tok_backward on N clips of
- * T x H x W (whole clips; the tape lives in it between the two calls). */
+ * T x H x W (whole clips; the tape lives in it between the two calls).  A
+ * workspace of this size also keeps every residual block's interior
+ * activations on the tape, so the backward does not recompute them. */
 tok_status tok_train_workspace_size(const tok_model* model, int N, int T, int H, int W, size_t* bytes);
+
+/* The smallest training workspace (per-block checkpointing): with fewer
+ * bytes than tok_train_workspace_size the backward recomputes each residual
+ * block's interior from the block input on the tape (same results, bit for
+ * bit, for two more GroupNorm+SiLU passes and one conv per block).  The
+ * forward and the backward of one step must get the same ws and ws_bytes. */
+tok_status tok_train_workspace_min_size(const tok_model* model, int N, int T, int H, int W, size_t* bytes);
 
 /* Forward pass of the objective.  x: uint8 (N,T,H,W,3).  keep: uint8
  * (N,T2,H2,W2) token mask (1 = kept) or NULL for all kept.  loss: device

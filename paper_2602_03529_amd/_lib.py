@@ -95,6 +95,8 @@ def lib():
     L.tok_model_set_weights.argtypes = [vp, vp, vp]
     L.tok_train_workspace_size.restype = i32
     L.tok_train_workspace_size.argtypes = [vp, i32, i32, i32, i32, C.POINTER(sz)]
+    L.tok_train_workspace_min_size.restype = i32
+    L.tok_train_workspace_min_size.argtypes = [vp, i32, i32, i32, i32, C.POINTER(sz)]
     L.tok_train_forward.restype = i32
     L.tok_train_forward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.tok_backward.restype = i32

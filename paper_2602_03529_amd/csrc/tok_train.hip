@@ -11,9 +11,11 @@
 //     upsample adjoint for the upsampling convs;
 //   * its weight and bias gradients come from the deterministic split-K
 //     weight-gradient kernel (fp32 MFMA);
-//   * each residual block recomputes its interior from its tape input
-//     (per-block checkpointing), then back-propagates through
-//     conv_b, GroupNorm_b+SiLU, conv_a, GroupNorm_a+SiLU and the skip;
+//   * each residual block takes its interior (GroupNorm_a+SiLU output,
+//     conv_a output, GroupNorm_b+SiLU output) from the tape when the
+//     workspace holds it, else recomputes it from its tape input (per-block
+//     checkpointing), then back-propagates through conv_b, GroupNorm_b+SiLU,
+//     conv_a, GroupNorm_a+SiLU and the skip;
 //   * FSQ passes the decoder gradient straight through (masked tokens pass
 //     none) and adds the commitment term's gradient.
 #include <algorithm>
@@ -40,6 +42,8 @@ struct TrainPlan {
   size_t D2, P, G2a, G2b;   // level 2 (128 channels)
   size_t Z, DEC, GZ, GDEC, KEEP, XHAT;
   size_t SC, SH, MR;        // per norm: N*T*64 scale, shift; N*T*32 (mean, rstd)
+  bool keep_rb;             // residual-block interiors kept on the tape (no recompute)
+  size_t RBI;               // [4 blocks][3] level-0 interior buffers when keep_rb
   size_t STATS, WP, WBP, GNP, FSUM, M12, L1P, CMP, O6P, LOSS;
   size_t total;
 };
@@ -65,10 +69,11 @@ std::vector<WgradShape> wgrad_shapes(const Dims& d) {
   return v;
 }
 
-TrainPlan make_train_plan(const Dims& d, int prec) {
+TrainPlan make_train_plan(const Dims& d, int prec, bool keep_rb) {
   const size_t es = prec == P_BF16 ? 2 : 4;
   TrainPlan p;
   p.d = d;
+  p.keep_rb = keep_rb;
   p.npos = (size_t)d.N * d.T * d.H * d.W;
   p.ntok = (size_t)d.N * d.T2 * d.H2 * d.W2;
   p.l0 = align256(p.npos * 64 * es);
@@ -102,6 +107,7 @@ TrainPlan make_train_plan(const Dims& d, int prec) {
   p.L1P = take((size_t)l1_blocks(p.npos) * 4); p.CMP = take((size_t)fsq_blocks(p.ntok) * 4);
   p.O6P = take(outer6_partial_floats(p.ntok) * 4);
   p.LOSS = take(4 * 4);
+  p.RBI = keep_rb ? take(12 * p.l0) : 0;
   p.total = o;
   return p;
 }
@@ -227,18 +233,27 @@ tok_status gn_bwd(const TrainCtx& c, int norm, const void* x, const void* g, con
   return TOK_OK;
 }
 
+// Interior buffer k (0: GroupNorm_a+SiLU output, 1: conv_a output, 2:
+// GroupNorm_b+SiLU output) of the residual block whose first conv is la.
+void* rb_interior(const TrainCtx& c, int la, int k) {
+  const int rb = la == L_E_RB1_A ? 0 : (la == L_E_RB2_A ? 1 : (la == L_D_RB1_A ? 2 : 3));
+  return c.at(c.p.RBI + (size_t)(rb * 3 + k) * c.p.l0);
+}
+
 // Residual block forward, out of place: Y = X + conv_b(silu(gn_b(conv_a(silu(gn_a X))))).
-// On entry the stats buffer holds X's per-tile GroupNorm partials.
+// On entry the stats buffer holds X's per-tile GroupNorm partials.  The
+// interior goes to the tape when it is kept, else to work buffers.
 tok_status rb_forward(const TrainCtx& c, int la, int na, const void* X, void* Y, bool out_stats) {
   const Dims& d = c.p.d;
-  void* S = c.at(c.p.S);
-  void* C = c.at(c.p.C);
+  void* S = c.p.keep_rb ? rb_interior(c, la, 0) : c.at(c.p.S);
+  void* C = c.p.keep_rb ? rb_interior(c, la, 1) : c.at(c.p.C);
+  void* S2 = c.p.keep_rb ? rb_interior(c, la, 2) : S;
   TOK_TRY(gn_final(c, na));
   TOK_TRY(gn_act(c, na, X, S));
   TOK_TRY(fwd(c, la, S, IN_ACT, d.T, d.H, d.W, C, OUT_ACT, d.T, d.H, d.W, nullptr, true));
   TOK_TRY(gn_final(c, na + 1));
-  TOK_TRY(gn_act(c, na + 1, C, S));
-  return fwd(c, la + 1, S, IN_ACT, d.T, d.H, d.W, Y, OUT_ACT, d.T, d.H, d.W, X, out_stats);
+  TOK_TRY(gn_act(c, na + 1, C, S2));
+  return fwd(c, la + 1, S2, IN_ACT, d.T, d.H, d.W, Y, OUT_ACT, d.T, d.H, d.W, X, out_stats);
 }
 
 // Residual block backward.  GB holds dL/dY on entry and dL/dX on exit.
@@ -250,17 +265,26 @@ tok_status rb_backward(const TrainCtx& c, int la, int na, const void* X, float* 
   void* GA = c.at(c.p.GA);
   void* GB = c.at(c.p.GB);
   const int lb = la + 1, nb = na + 1;
-  // recompute the interior from the block input and the forward's statistics
-  TOK_TRY(gn_act(c, na, X, S));
-  TOK_TRY(fwd(c, la, S, IN_ACT, d.T, d.H, d.W, C, OUT_ACT, d.T, d.H, d.W, nullptr, false));
-  TOK_TRY(gn_act(c, nb, C, S2));
+  // the interior: from the tape, or recomputed from the block input and the forward's statistics
+  const void* Si = S;
+  const void* Ci = C;
+  const void* S2i = S2;
+  if (c.p.keep_rb) {
+    Si = rb_interior(c, la, 0);
+    Ci = rb_interior(c, la, 1);
+    S2i = rb_interior(c, la, 2);
+  } else {
+    TOK_TRY(gn_act(c, na, X, S));
+    TOK_TRY(fwd(c, la, S, IN_ACT, d.T, d.H, d.W, C, OUT_ACT, d.T, d.H, d.W, nullptr, false));
+    TOK_TRY(gn_act(c, nb, C, S2));
+  }
   // conv_b
-  TOK_TRY(wgrad(c, lb, CM_S1, S2, d.T, d.H, d.W, GB, d.T, d.H, d.W, dweights));
+  TOK_TRY(wgrad(c, lb, CM_S1, S2i, d.T, d.H, d.W, GB, d.T, d.H, d.W, dweights));
   TOK_TRY(adj(c, lb, GB, d.T, d.H, d.W, GA, OUT_ACT));
   // GroupNorm_b + SiLU (in place on GA)
-  TOK_TRY(gn_bwd(c, nb, C, GA, nullptr, GA, dweights));
+  TOK_TRY(gn_bwd(c, nb, Ci, GA, nullptr, GA, dweights));
   // conv_a
-  TOK_TRY(wgrad(c, la, CM_S1, S, d.T, d.H, d.W, GA, d.T, d.H, d.W, dweights));
+  TOK_TRY(wgrad(c, la, CM_S1, Si, d.T, d.H, d.W, GA, d.T, d.H, d.W, dweights));
   TOK_TRY(adj(c, la, GA, d.T, d.H, d.W, C, OUT_ACT));
   // GroupNorm_a + SiLU, plus the skip path
   return gn_bwd(c, na, X, C, GB, GB, dweights);
@@ -276,7 +300,11 @@ bool check_ws(const tok_model* m, int N, int T, int H, int W, size_t ws_bytes, T
     *st = fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
     return false;
   }
-  *p = make_train_plan(d, m->prec);
+  // a workspace that holds the residual-block interiors keeps them; a
+  // smaller one (at least the checkpointing size) makes the backward recompute them
+  *p = make_train_plan(d, m->prec, true);
+  if (p->total <= ws_bytes) return true;
+  *p = make_train_plan(d, m->prec, false);
   if (p->total > ws_bytes) {
     *st = fail(TOK_EWORKSPACE, "training workspace needs " + std::to_string(p->total) + " bytes");
     return false;
@@ -293,7 +321,16 @@ tok_status tok_train_workspace_size(const tok_model* m, int N, int T, int H, int
   if (m->prec == P_FP8) return fail(TOK_EUNSUPPORTED, "training needs an f32 or bf16 model");
   Dims d;
   if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
-  *bytes = make_train_plan(d, m->prec).total;
+  *bytes = make_train_plan(d, m->prec, true).total;
+  return TOK_OK;
+}
+
+tok_status tok_train_workspace_min_size(const tok_model* m, int N, int T, int H, int W, size_t* bytes) {
+  if (!m || !bytes) return fail(TOK_EINVAL, "null argument");
+  if (m->prec == P_FP8) return fail(TOK_EUNSUPPORTED, "training needs an f32 or bf16 model");
+  Dims d;
+  if (!make_dims(N, T, H, W, &d)) return fail(TOK_ESHAPE, "need N>=1, T%4==1, H%4==0, W%4==0");
+  *bytes = make_train_plan(d, m->prec, false).total;
   return TOK_OK;
 }
 

@@ -142,9 +142,16 @@ class TokModel:
         _need(w, torch.float32, (weight_count(),), "weights")
         L.check("tok_model_set_weights", self.lib.tok_model_set_weights(self.handle, _ptr(w), _stream(w.device)))
 
-    def train_workspace_size(self, N, T, H, W) -> int:
+    def train_workspace_size(self, N, T, H, W, recompute=False) -> int:
+        """Training workspace bytes.  The default size keeps every residual
+        block's interior on the tape; recompute=True gives the smallest one,
+        with which the backward recomputes them (same gradients, bit for bit)."""
         n = C.c_size_t()
-        L.check("tok_train_workspace_size", self.lib.tok_train_workspace_size(self.handle, N, T, H, W, C.byref(n)))
+        if recompute:
+            L.check("tok_train_workspace_min_size",
+                    self.lib.tok_train_workspace_min_size(self.handle, N, T, H, W, C.byref(n)))
+        else:
+            L.check("tok_train_workspace_size", self.lib.tok_train_workspace_size(self.handle, N, T, H, W, C.byref(n)))
         return int(n.value)
 
     def train_forward(self, x: torch.Tensor, keep: torch.Tensor | None = None, ws: torch.Tensor | None = None,

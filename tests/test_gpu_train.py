@@ -175,6 +175,27 @@ def test_backward_deterministic_and_scaled(tk):
     assert rel_l2(c.cpu().numpy(), 2.5 * a.cpu().numpy().astype(np.float64)) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_checkpointed_backward_equals_kept_interiors(tk, prec):
+    """The smallest workspace makes the backward recompute each residual
+    block's interior (per-block checkpointing); the default one keeps the
+    interiors on the tape.  Loss, weight and input gradients agree bit for bit."""
+    m = model(tk, prec)
+    N, T, H, W = 2, 5, 36, 72
+    x = torch.from_numpy(G.clip((0, 1), T, H, W)).cuda()
+    full, small = m.train_workspace_size(N, T, H, W), m.train_workspace_size(N, T, H, W, recompute=True)
+    assert small < full
+    fk = m.train_forward(x)
+    gk = m.backward(x, fk["ws"], dx=True)
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    fr = m.train_forward(x, ws=ws)
+    gr = m.backward(x, ws, dx=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fk["loss"], fr["loss"])
+    assert torch.equal(gk["dweights"], gr["dweights"])
+    assert torch.equal(gk["dx"], gr["dx"])
+
+
 def test_autograd_function_matches_direct_call(tk):
     from paper_2602_03529_amd.tok import tokenizer_loss
     m = tk.TokModel(synth.flatten_weights(G.weights(False)), "f32")
