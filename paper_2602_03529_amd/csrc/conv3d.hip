@@ -870,22 +870,36 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
       if constexpr (STATS) {
         const int vr = min(G::TH, a.Ho - h0), vc = min(G::TW, a.Wo - w0);
         const float cnt = 2.0f * (float)(vr * vc);
+        // Group sums through LDS (the K loop's halo buffer): lane (wave, hh,
+        // p32) puts its partials of groups 16 c + 4 q + 2 hh (+1) at row g,
+        // column 32 wave + p32 (rows 136 floats apart, so that the readers
+        // below hit distinct banks); thread t then adds 16 values of row t / 8
+        // and three shuffles finish the row.  Fixed order: deterministic.
+        float* red2 = reinterpret_cast<float*>(&lds_a[0][0]);
+        static_assert(32 * 136 * 4 <= HQ * 16, "group partials fit the halo buffer");
+        const int rg = tid >> 3, rp = tid & 7;
+        auto row_total = [&]() {
+          float t = 0.f;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) t += red2[rg * 136 + u * 8 + rp];
+          t += __shfl_xor(t, 1);
+          t += __shfl_xor(t, 2);
+          t += __shfl_xor(t, 4);
+          return t;
+        };
+        __syncthreads();  // every wave is done with the K loop's LDS
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-#pragma unroll
-          for (int o = 1; o < 32; o <<= 1) {
-            s_lo[k] += __shfl_xor(s_lo[k], o);
-            s_hi[k] += __shfl_xor(s_hi[k], o);
-          }
-          if (p32 == 0) {
-            const int g = 16 * (k >> 2) + 4 * (k & 3) + 2 * hh;
-            red[wave][g] = s_lo[k];
-            red[wave][g + 1] = s_hi[k];
-          }
+          const int g = 16 * (k >> 2) + 4 * (k & 3) + 2 * hh;
+          red2[g * 136 + wave * 32 + p32] = s_lo[k];
+          red2[(g + 1) * 136 + wave * 32 + p32] = s_hi[k];
         }
         __syncthreads();
-        if (tid < 32) gmean[tid] = (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) / cnt;
-        __syncthreads();
+        {
+          const float t = row_total();
+          if (rp == 0) gmean[rg] = t / cnt;
+        }
+        __syncthreads();  // gmean is set and every row is read
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int c = k >> 2, q = k & 3;
@@ -901,29 +915,17 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
               qb += d2 * d2 + d3 * d3;
             }
           }
-          s_lo[k] = qa;
-          s_hi[k] = qb;
-#pragma unroll
-          for (int o = 1; o < 32; o <<= 1) {
-            s_lo[k] += __shfl_xor(s_lo[k], o);
-            s_hi[k] += __shfl_xor(s_hi[k], o);
-          }
+          red2[g * 136 + wave * 32 + p32] = qa;
+          red2[(g + 1) * 136 + wave * 32 + p32] = qb;
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (p32 == 0) {
-            const int g = 16 * (k >> 2) + 4 * (k & 3) + 2 * hh;
-            red[wave][g] = s_lo[k];
-            red[wave][g + 1] = s_hi[k];
+        {
+          const float m2 = row_total();
+          if (rp == 0) {
+            const int tiles = a.tiles_h * a.tiles_w;
+            a.stats[(((size_t)n * a.To + to) * tiles + (size_t)th * a.tiles_w + tw) * 32 + rg] =
+                make_float4(cnt, gmean[rg], m2, 0.f);
           }
-        }
-        __syncthreads();
-        if (tid < 32) {
-          const float m2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-          const int tiles = a.tiles_h * a.tiles_w;
-          a.stats[(((size_t)n * a.To + to) * tiles + (size_t)th * a.tiles_w + tw) * 32 + tid] =
-              make_float4(cnt, gmean[tid], m2, 0.f);
         }
       }
       return;
@@ -1240,21 +1242,42 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
     // Requires nt == Cout == 64 (32 groups), checked on the host.
     const int vr = min(G::TH, a.Ho - h0), vc = min(G::TW, a.Wo - w0);
     const float cnt = 2.0f * (float)(vr * vc);
+    // Group sums through LDS (a buffer the K loop no longer needs): lane
+    // (wave, g4, l16) puts its partials of groups 8 b + 2 g4 (+1) at row g,
+    // column 16 wave + l16 (rows 72 floats apart, so that the readers below
+    // hit distinct banks); thread t then adds 8 values of row t / 8 and three
+    // shuffles finish the row.  Fixed order: deterministic.
+    float* red2;
+    if constexpr (MODE == CM_I2C) {
+      if constexpr (PXH16) red2 = reinterpret_cast<float*>(lds_pxh);
+      else red2 = lds_px;
+      static_assert(MODE != CM_I2C || 32 * 72 * 4 <= PXN * (PXH16 ? 2 : 4), "group partials fit the pixel tile");
+    } else {
+      red2 = reinterpret_cast<float*>(&lds_a[0][0]);
+      static_assert(MODE == CM_I2C || 32 * 72 * 4 <= HQ * 16, "group partials fit the halo buffer");
+    }
+    const int rg = tid >> 3, rp = tid & 7;
+    auto row_total = [&]() {
+      float t = 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += red2[rg * 72 + u * 8 + rp];
+      t += __shfl_xor(t, 1);
+      t += __shfl_xor(t, 2);
+      t += __shfl_xor(t, 4);
+      return t;
+    };
+    __syncthreads();  // every wave is done with the K loop's LDS
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        s_lo[b] += __shfl_xor(s_lo[b], off);
-        s_hi[b] += __shfl_xor(s_hi[b], off);
-      }
-      if (l16 == 0) {
-        red[wave][b * 8 + 2 * g4] = s_lo[b];
-        red[wave][b * 8 + 2 * g4 + 1] = s_hi[b];
-      }
+      red2[(b * 8 + 2 * g4) * 72 + wave * 16 + l16] = s_lo[b];
+      red2[(b * 8 + 2 * g4 + 1) * 72 + wave * 16 + l16] = s_hi[b];
     }
     __syncthreads();
-    if (tid < 32) gmean[tid] = (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) / cnt;
-    __syncthreads();
+    {
+      const float t = row_total();
+      if (rp == 0) gmean[rg] = t / cnt;
+    }
+    __syncthreads();  // gmean is set and every row is read
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const float ma = gmean[b * 8 + 2 * g4], mb = gmean[b * 8 + 2 * g4 + 1];
@@ -1270,28 +1293,17 @@ __global__ void __launch_bounds__(kThreads, (MODE == CM_I2C && PREC == P_BF16) ?
           qb += d2 * d2 + d3 * d3;
         }
       }
-      s_lo[b] = qa;
-      s_hi[b] = qb;
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        s_lo[b] += __shfl_xor(s_lo[b], off);
-        s_hi[b] += __shfl_xor(s_hi[b], off);
-      }
+      red2[(b * 8 + 2 * g4) * 72 + wave * 16 + l16] = qa;
+      red2[(b * 8 + 2 * g4 + 1) * 72 + wave * 16 + l16] = qb;
     }
     __syncthreads();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (l16 == 0) {
-        red[wave][b * 8 + 2 * g4] = s_lo[b];
-        red[wave][b * 8 + 2 * g4 + 1] = s_hi[b];
+    {
+      const float m2 = row_total();
+      if (rp == 0) {
+        const int tiles = a.tiles_h * a.tiles_w;
+        a.stats[(((size_t)n * a.To + to) * tiles + (size_t)th * a.tiles_w + tw) * 32 + rg] =
+            make_float4(cnt, gmean[rg], m2, 0.f);
       }
-    }
-    __syncthreads();
-    if (tid < 32) {
-      const float m2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      const int tiles = a.tiles_h * a.tiles_w;
-      a.stats[(((size_t)n * a.To + to) * tiles + (size_t)th * a.tiles_w + tw) * 32 + tid] =
-          make_float4(cnt, gmean[tid], m2, 0.f);
     }
   }
 }
