@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # by the same counters on a 1 GiB device copy; see profiles/.  Valid for that
 # workload and the conv kernel as measured; other shapes report null, and so
 # does this one while the kernel has changed since the counters were taken.
-RB_CONV_HBM_BYTES_720P = 22.45e9
+RB_CONV_HBM_BYTES_720P = 22.47e9
 F32_PEAK_TFLOPS = 157.3
 # Useful FLOPs per output position of each conv (2 * taps * Cin * Cout) and
 # the level it runs at.  The 3x3x3 convs take 27 taps, except the upsampling
