@@ -85,9 +85,10 @@ template <> struct Geo<CM_UPT> {
 // workgroup tile): an activation operand loaded for halo row r then serves
 // output rows r - kh for every kh, a third fewer LDS reads than 2 x 64 rows.
 
-// Workgroups per CU the bf16 first-layer kernel is compiled for (at three
-// its registers spill).
-constexpr int kI2cOcc = 2;
+// Workgroups per CU the bf16 first-layer kernel is compiled for (three since
+// its GroupNorm partials are reduced through LDS: 2 VGPRs spill, against 53
+// with the shuffle trees).
+constexpr int kI2cOcc = 3;
 
 // Output-tile-local position of lane l16 in position block m of a wave.
 template <int MODE>
