@@ -89,7 +89,9 @@ def test_drop_external_mask(tk):
 SHAPES = [((0,), 9, 64, 64, False),        # the 1x9x64x64 configuration
           ((0, 1), 5, 40, 72, True),       # ragged tiles in h and w, random bias / affine
           ((3,), 1, 16, 132, True),        # single frame, W not a multiple of the 64-wide tile
-          ((2,), 13, 24, 24, False)]       # more frames, several latent frames
+          ((2,), 13, 24, 24, False),       # more frames, several latent frames
+          ((1,), 1, 4, 4, True),           # the smallest frame: one latent position, tiles almost all padding
+          ((0,), 5, 4, 8, False)]          # one latent row of two positions
 
 
 @pytest.mark.parametrize("seeds,T,H,W,ra", SHAPES)
