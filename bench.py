@@ -332,14 +332,15 @@ def fp8_leg(tok, synth, wflat, dev, args):
     return out
 
 
-def coding_leg(tok, x, xhat, codes, idx, args):
+def coding_leg(tok, x, xhat, codes, idx, args, model=None):
     """The coding steps around the tokenizer on the headline batch's own
     tensors: similarity-based token selection (Sec. 4.3, Eq. 3) on its codes,
     row packets and reassembly (Sec. 6.2), the pixel-residual layer (Sec. 4.3,
     Eq. 4) on its clips and reconstructions, GoP-boundary blending (Sec. 4.2,
     Eq. 2).  Per op: time per call (HIP events on the launching stream) and
     algorithmic bytes / time against the 8 TB/s HBM peak (all are HBM- or
-    launch-bound)."""
+    launch-bound).  With the model: the decode with the residual sums fused
+    into its last layer against the plain decode."""
     import torch
     s = torch.cuda.current_stream()
 
@@ -399,6 +400,16 @@ def coding_leg(tok, x, xhat, codes, idx, args):
     px = N * H * W * 3
     out["residual_compress"] = entry(ms, px * T * 5 + px * 4 + nnz * 8, theta=theta, nonzero=nnz,
                                      note="untrained stand-in weights: the residual is dense")
+    if model is not None:
+        xh2 = torch.empty_like(xhat)
+        ms_dec = timed_op(lambda: model.decode(codes, out=xh2), iters=5)
+        ms_fused = timed_op(lambda: model.decode_residual(codes, x, theta, out=xh2), iters=5)
+        out["decode_residual_fused"] = dict(
+            decode_us=round(ms_dec * 1e3, 1), decode_residual_us=round(ms_fused * 1e3, 1),
+            added_us=round((ms_fused - ms_dec) * 1e3, 1),
+            separate_residual_compress_us=out["residual_compress"]["us_per_call"],
+            note="residual sums formed by the last conv while it writes each frame, then threshold and compaction")
+        del xh2
     r = res["r"]
     ms = timed_op(lambda: tok.residual_apply(r, xhat))
     out["residual_apply"] = entry(ms, px * 4 + px * T * 8)
@@ -578,7 +589,7 @@ def main():
     coding = None
     if args.coding:
         enc = mb.encode(x, z=False, keep=False)
-        coding = coding_leg(tok, x, xh_b, enc["codes"], enc["idx"], args)
+        coding = coding_leg(tok, x, xh_b, enc["codes"], enc["idx"], args, model=mb)
         del enc
         print("bench: coding leg done", file=sys.stderr, flush=True)
 

@@ -268,6 +268,24 @@ tok_status tok_decode_blend(tok_model* model, const float* codes, int N, int T2,
                             const float* prev, int T_prev, int n, float* xhat, void* ws,
                             size_t ws_bytes, hipStream_t stream);
 
+/* tok_decode followed by tok_residual_compress of the decoded clip (Sec. 4.3,
+ * Eq. 4; the averaging window is the clip's T = 4(T2-1)+1 frames), with the
+ * residual sums fused into C_out (bf16 and fp8 models): as the last layer
+ * writes each frame of x_hat it adds x_t/127.5 - 1 - x_hat_t, in fp32 and in
+ * frame order, into r, so the separate pass over the T frames of x and x_hat
+ * is not needed; then r becomes the thresholded mean and its non-zero
+ * entries are listed.  Results equal tok_decode then tok_residual_compress
+ * bit for bit (fp32 models run exactly that).  x: uint8 (N,T,4 H2,4 W2,3)
+ * source clips (device, 16-byte aligned); xhat, ws, ws_bytes as tok_decode;
+ * r, index, value, capacity, clip_offsets as tok_residual_compress; rs_ws:
+ * device scratch of tok_residual_workspace_size(N, 4 H2, 4 W2) bytes.
+ * r's contents on entry are overwritten; r, xhat and x must not overlap.
+ * Errors as tok_decode and tok_residual_compress. */
+tok_status tok_decode_residual(tok_model* model, const float* codes, int N, int T2, int H2, int W2,
+                               const uint8_t* x, float theta, float* xhat, float* r, uint32_t* index,
+                               float* value, size_t capacity, uint64_t* clip_offsets, void* ws,
+                               size_t ws_bytes, void* rs_ws, size_t rs_ws_bytes, hipStream_t stream);
+
 /* Decoder g_theta: codes float32 (N,T2,H2,W2,6) -> x_hat float32
  * (N, 4(T2-1)+1, 4 H2, 4 W2, 3). */
 tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H2, int W2,

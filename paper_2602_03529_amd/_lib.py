@@ -90,6 +90,9 @@ def lib():
     L.tok_gop_blend.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, vp]
     L.tok_decode_blend.restype = i32
     L.tok_decode_blend.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, sz, vp]
+    L.tok_decode_residual.restype = i32
+    L.tok_decode_residual.argtypes = [vp, vp, i32, i32, i32, i32, vp, C.c_float, vp, vp, vp, vp, sz, vp, vp, sz, vp,
+                                      sz, vp]
     L.tok_decode.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
     L.tok_model_set_weights.restype = i32
     L.tok_model_set_weights.argtypes = [vp, vp, vp]

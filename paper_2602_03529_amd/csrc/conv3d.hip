@@ -146,6 +146,14 @@ __device__ __forceinline__ void lds_dma16(const uint4* g, uint4* lds_wave_base) 
   __builtin_amdgcn_global_load_lds(g, lds_wave_base, 16, 0, 0);
 }
 
+// The same through a buffer resource: base and size in scalar registers, one
+// 32-bit byte offset per lane (offsets past the size read zeros).  Needs no
+// per-slot 64-bit addresses, which register-tight kernels otherwise keep in
+// spill slots and reload, each reload waiting for the transfers in flight.
+__device__ __forceinline__ void lds_dma16_buf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint4* lds_wave_base) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds_wave_base, 16, voff, 0, 0, 0);
+}
+
 template <int PREC>
 __device__ __forceinline__ void mfma_quad(f32x4& acc, const uint4& wq, const uint4& aq) {
   if constexpr (PREC == P_BF16) {
@@ -1342,7 +1350,7 @@ hipError_t launch_one(const ConvLaunch& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int kWalkHW = 66, kWalkHalo = 10 * kWalkHW, kWalkHQ = kWalkHalo * 4;
 
-template <int PREC>
+template <int PREC, bool RS>
 __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a) {
   constexpr bool F8 = PREC == P_FP8;
   constexpr int NCK = F8 ? 1 : 2;  // input chunks (64 channels)
@@ -1405,6 +1413,17 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
   float o0[8], o1[8], o2[8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) o0[m] = o1[m] = o2[m] = init;
+  // pixel-residual sums of this lane's 8 positions (colour g4), carried over
+  // from the clip's earlier chunks
+  const bool rs_on = RS && g4 < 3;
+  float rsum[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    rsum[m] = 0.f;
+    const int oh = h0 + 2 * wave + (m >> 2), ow = w0 + (m & 3) * 16 + l16;
+    if (rs_on && a.go0 > 0 && oh < a.Ho && ow < a.Wo)
+      rsum[m] = a.rs_sum[(((size_t)n * a.Ho + oh) * a.Wo + ow) * 3 + g4];
+  }
 
   const int f_first = max(a.go0 - 2, 0), f_end = a.go0 + a.To;
   for (int fg = f_first; fg < f_end; ++fg) {
@@ -1428,8 +1447,12 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
       for (int k = 0; k < NHS; ++k) {
         const int base = wave * 64 + k * kThreads, e = base + lane;
         if (e < kWalkHQ) {
-          if (hoff[k] >= 0) lds_dma16(src + hoff[k], &lds_h[base]);
-          else lds_h[e] = make_uint4(0, 0, 0, 0);
+          if (hoff[k] < 0) lds_h[e] = make_uint4(0, 0, 0, 0);
+          else if constexpr (RS)  // (the plane is below 2^31 bytes, checked on the host)
+            lds_dma16_buf(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint4*>(src), (short)0,
+                                                            (int)(plane_in * 64), 0x00020000),
+                          (uint32_t)hoff[k] * 16u, &lds_h[base]);
+          else lds_dma16(src + hoff[k], &lds_h[base]);
         }
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1518,6 +1541,10 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
         }
         reinterpret_cast<float*>(a.out)[(((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3 +
                                         g4] = y;
+        if (rs_on) {
+          const uint32_t u = a.rs_x[(((size_t)n * a.rs_T + fg) * plane_out + (size_t)oh * a.Wo + ow) * 3 + g4];
+          rsum[m] += ((float)u / 127.5f - 1.0f) - y;
+        }
       }
     }
 #pragma unroll
@@ -1525,6 +1552,13 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
       o0[m] = o1[m];
       o1[m] = o2[m];
       o2[m] = init;
+    }
+  }
+  if (rs_on) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int oh = h0 + 2 * wave + (m >> 2), ow = w0 + (m & 3) * 16 + l16;
+      if (oh < a.Ho && ow < a.Wo) a.rs_sum[(((size_t)n * a.Ho + oh) * a.Wo + ow) * 3 + g4] = rsum[m];
     }
   }
 }
@@ -1537,9 +1571,11 @@ hipError_t launch_rgb_walk(const ConvLaunch& a, hipStream_t s) {
   if (a.Cout != 3 || a.nt != 16 || a.in_chunks > (PREC == P_FP8 ? 1 : 2) || a.gi0 > (a.go0 > 2 ? a.go0 - 2 : 0) ||
       a.go0 + a.To - a.gi0 > a.Ti)
     return hipErrorInvalidValue;
+  if (a.rs_sum && (!a.rs_x || a.go0 + a.To > a.rs_T)) return hipErrorInvalidValue;  // residual sums: source frames
   const long long nb = (long long)a.N * a.tiles_h * a.tiles_w;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(conv_rgb_walk_kernel<PREC>, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  if (a.rs_sum) hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, true>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, false>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1555,6 +1591,7 @@ hipError_t dispatch_prec(const ConvLaunch& a, hipStream_t s) {
   if (a.out_kind == OUT_RGB32) {
     if (a.mode == CM_S1 && a.nt == 16 && !res && !st) {
       if constexpr (PREC == P_BF16) return launch_rgb_walk<P_BF16>(a, s);
+      if (a.rs_sum) return hipErrorInvalidValue;  // residual sums: the frame-walking kernel only
       return launch_one<PREC, CM_S1, 1, IN_ACT, OUT_RGB32, false, false>(a, s);
     }
     if (a.mode == CM_S1T && a.nt == 16 && !res && !st)

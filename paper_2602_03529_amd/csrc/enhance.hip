@@ -6,6 +6,8 @@
 //                      frame order; entries with |r| < theta become 0; writes
 //                      the dense thresholded residual and each block's count
 //                      of non-zero entries
+//   rs_finish_kernel   the same from sums the decoder's last layer accumulated
+//                      while writing x_hat (in place)
 //   rs_scan_kernel     one workgroup: exclusive scan of the block counts
 //   rs_compact_kernel  the non-zero entries of each clip as (flat index
 //                      (h W + w) 3 + c, value) in increasing index order
@@ -24,6 +26,32 @@ constexpr int kRsBlock = kRsThreads * kRsVec;     // entries per block
 constexpr int kScanThreads = 1024;
 
 __device__ __forceinline__ float px(uint32_t u) { return (float)u / 127.5f - 1.0f; }
+
+// r = sum / T with entries of magnitude below theta set to 0; returns the
+// number of non-zero entries.
+__device__ __forceinline__ int rs_mean4(float s[4], int T, float theta) {
+  const float fT = (float)T;
+  int nz = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float r = s[k] / fT;
+    s[k] = fabsf(r) < theta ? 0.f : r;
+    nz += s[k] != 0.f;
+  }
+  return nz;
+}
+
+// The block's count of non-zero entries (wave sums by shuffles, then the 4
+// waves) into counts[slot].
+__device__ __forceinline__ void rs_block_count(int nz, uint32_t* wsum, uint32_t* counts, size_t slot) {
+  const int tid = threadIdx.x;
+  int v = nz;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((tid & 63) == 0) wsum[tid >> 6] = (uint32_t)v;
+  __syncthreads();
+  if (tid == 0) counts[slot] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
 
 // grid (blocks per clip, N); E = H W 3 entries per frame (a multiple of 16).
 // A thread owns 4 consecutive entries (a wave one contiguous 1 KB run of
@@ -49,22 +77,30 @@ __global__ void __launch_bounds__(kRsThreads) rs_mean_kernel(const uint8_t* __re
       s2 += px((u >> 16) & 255u) - h.z;
       s3 += px(u >> 24) - h.w;
     }
-    const float fT = (float)T;
-    float r0 = s0 / fT, r1 = s1 / fT, r2 = s2 / fT, r3 = s3 / fT;
-    r0 = fabsf(r0) < theta ? 0.f : r0;
-    r1 = fabsf(r1) < theta ? 0.f : r1;
-    r2 = fabsf(r2) < theta ? 0.f : r2;
-    r3 = fabsf(r3) < theta ? 0.f : r3;
-    *reinterpret_cast<float4*>(rs + (size_t)n * E + e) = make_float4(r0, r1, r2, r3);
-    nz = (r0 != 0.f) + (r1 != 0.f) + (r2 != 0.f) + (r3 != 0.f);
+    float r[4] = {s0, s1, s2, s3};
+    nz = rs_mean4(r, T, theta);
+    *reinterpret_cast<float4*>(rs + (size_t)n * E + e) = make_float4(r[0], r[1], r[2], r[3]);
   }
-  // block count: wave sums by shuffles, then the 4 waves
-  int v = nz;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((tid & 63) == 0) wsum[tid >> 6] = (uint32_t)v;
-  __syncthreads();
-  if (tid == 0) counts[(size_t)n * gridDim.x + blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  rs_block_count(nz, wsum, counts, (size_t)n * gridDim.x + blockIdx.x);
+}
+
+// Same grid as rs_mean_kernel: rs holds sum_t (x_t / 127.5 - 1 - x_hat_t)
+// per entry (accumulated in frame order by the decoder's last layer) and is
+// replaced by the thresholded mean.
+__global__ void __launch_bounds__(kRsThreads) rs_finish_kernel(float* __restrict__ rs, int T, long long E,
+                                                                float theta, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t wsum[kRsThreads / 64];
+  const int n = blockIdx.y, tid = threadIdx.x;
+  const long long e = ((long long)blockIdx.x * kRsThreads + tid) * kRsVec;
+  int nz = 0;
+  if (e < E) {
+    float4* p = reinterpret_cast<float4*>(rs + (size_t)n * E + e);
+    const float4 v = *p;
+    float r[4] = {v.x, v.y, v.z, v.w};
+    nz = rs_mean4(r, T, theta);
+    *p = make_float4(r[0], r[1], r[2], r[3]);
+  }
+  rs_block_count(nz, wsum, counts, (size_t)n * gridDim.x + blockIdx.x);
 }
 
 // counts[0..B) -> exclusive prefix sums in place; counts[B] = total.
@@ -196,6 +232,20 @@ hipError_t launch_residual(const uint8_t* x, const float* xhat, int N, int T, in
   uint32_t* counts = static_cast<uint32_t*>(ws);
   const dim3 grid((unsigned)bpc, N);
   hipLaunchKernelGGL(rs_mean_kernel, grid, dim3(kRsThreads), 0, s, x, xhat, T, E, theta, rs, counts);
+  hipLaunchKernelGGL(rs_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, (long long)N * bpc);
+  hipLaunchKernelGGL(rs_compact_kernel, grid, dim3(kRsThreads), 0, s, rs, E, counts, index, value, capacity,
+                     clip_off, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_sums(float* rs, int N, int T, int H, int W, float theta, uint32_t* index, float* value,
+                                long long capacity, unsigned long long* clip_off, void* ws, hipStream_t s) {
+  const long long E = 3LL * H * W, bpc = (E + kRsBlock - 1) / kRsBlock;
+  if (N < 1 || N > 65535 || T < 1 || E < 16 || (E & 15) || bpc > 0x7fffffffLL || (long long)N * E >= 0xffffffffLL)
+    return hipErrorInvalidValue;
+  uint32_t* counts = static_cast<uint32_t*>(ws);
+  const dim3 grid((unsigned)bpc, N);
+  hipLaunchKernelGGL(rs_finish_kernel, grid, dim3(kRsThreads), 0, s, rs, T, E, theta, counts);
   hipLaunchKernelGGL(rs_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, (long long)N * bpc);
   hipLaunchKernelGGL(rs_compact_kernel, grid, dim3(kRsThreads), 0, s, rs, E, counts, index, value, capacity,
                      clip_off, N);

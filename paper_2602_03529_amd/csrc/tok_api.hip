@@ -162,6 +162,14 @@ struct Blend {
   int Tp, n;
 };
 
+// Pixel-residual sums accumulated by C_out as it writes each frame
+// (tok_decode_residual): source clip x (T frames) and the (N, H, W, 3) sums.
+struct ResAcc {
+  const uint8_t* x;
+  float* sum;
+  int T;
+};
+
 const char* kKernelNames[K_IDS] = {
     "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
     "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
@@ -173,13 +181,18 @@ const char* kKernelNames[K_IDS] = {
 tok_status conv(const tok_model* m, int layer, int mode, const void* in, int in_kind, int N, const Win& iw, int Hi,
                 int Wi, int Cin, void* out, int out_kind, const Win& ow, int Ho, int Wo, const void* resid,
                 float4* stats, hipStream_t s, const uint8_t* in_scale = nullptr, uint8_t* out_scale = nullptr,
-                const Blend* blend = nullptr) {
+                const Blend* blend = nullptr, const ResAcc* racc = nullptr) {
   ConvLaunch a;
   std::memset(&a, 0, sizeof(a));
   if (blend) {
     a.blend_prev = blend->prev;
     a.blend_Tp = blend->Tp;
     a.blend_n = blend->n;
+  }
+  if (racc) {
+    a.rs_x = racc->x;
+    a.rs_sum = racc->sum;
+    a.rs_T = racc->T;
   }
   const int CH = m->prec == P_BF16 ? 32 : (m->prec == P_FP8 ? 64 : 16);  // input chunking
   const int CHo = out_kind == OUT_FP8 ? 64 : (m->prec == P_F32 ? 16 : 32);
@@ -446,8 +459,7 @@ Fp8Plan make_fp8_plan(const Dims& d) {
 }
 
 tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xhat, void* ws, size_t ws_bytes,
-                      hipStream_t s,
-                      const Blend* blend) {
+                      hipStream_t s, const Blend* blend, const ResAcc* racc) {
   const Fp8Plan p = make_fp8_plan(d);
   if (p.total > ws_bytes)
     return fail(TOK_EWORKSPACE, "fp8 decode workspace needs " + std::to_string(p.total) + " bytes");
@@ -492,7 +504,7 @@ tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xh
                    s, u8(p.Ssc), u8(p.Csc)));
   }
   return conv(m, L_CONV_OUT, CM_S1, at(p.C), IN_ACT, N, w0, H, W, 64, xhat, OUT_RGB32, w0, H, W, nullptr, nullptr, s,
-              u8(p.Csc), nullptr, blend);
+              u8(p.Csc), nullptr, blend, racc);
 }
 
 }  // namespace
@@ -782,7 +794,7 @@ tok_status tok_select_scratch_bytes(size_t* bytes) {
 namespace {
 
 tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, int W2, float* xhat, void* ws,
-                       size_t ws_bytes, hipStream_t s, const Blend* blend) {
+                       size_t ws_bytes, hipStream_t s, const Blend* blend, const ResAcc* racc = nullptr) {
   if (!m || !codes || !xhat || !ws) return fail(TOK_EINVAL, "null argument");
   if (T2 < 1 || H2 < 1 || W2 < 1) return fail(TOK_ESHAPE, "bad latent shape");
   Dims d;
@@ -790,7 +802,7 @@ tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, 
   if (blend && (!blend->prev || blend->n < 1 || blend->n > d.T || blend->n > blend->Tp ||
                 (reinterpret_cast<uintptr_t>(blend->prev) & 3)))
     return fail(TOK_EINVAL, "blend needs a 4-byte aligned prev and 1 <= n <= T, T_prev");
-  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend);
+  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend, racc);
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))
     return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
@@ -815,7 +827,7 @@ tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, 
     TOK_TRY(resblocks(m, L_D_RB1_A, N_D_RB1_A, w, d, c.l0, false, chunked, L0, s));
     const Win ow{d.T, 0, c.l0.g0 + c.l0.first, c.l0.count};
     TOK_TRY(conv(m, L_CONV_OUT, CM_S1, w.l0a(), IN_ACT, N, c.l0, d.H, d.W, 64, xhat, OUT_RGB32, ow, d.H, d.W, nullptr,
-                 nullptr, s, nullptr, nullptr, blend));
+                 nullptr, s, nullptr, nullptr, blend, racc));
     if (L1 < d.T2) {
       TOK_TRY(shift_cache(w.l2(), c.l2, N, f2b, kCache2, s));
       TOK_TRY(shift_cache(w.l1(), c.l1, N, f1b, kCache1, s));
@@ -836,6 +848,32 @@ tok_status tok_decode_blend(tok_model* m, const float* codes, int N, int T2, int
                             int T_prev, int n, float* xhat, void* ws, size_t ws_bytes, hipStream_t s) {
   const Blend b{prev, T_prev, n};
   return decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, &b);
+}
+
+tok_status tok_decode_residual(tok_model* m, const float* codes, int N, int T2, int H2, int W2, const uint8_t* x,
+                               float theta, float* xhat, float* r, uint32_t* index, float* value, size_t capacity,
+                               uint64_t* clip_offsets, void* ws, size_t ws_bytes, void* rs_ws, size_t rs_ws_bytes,
+                               hipStream_t s) {
+  if (!m || !x || !r || !clip_offsets || !rs_ws || (capacity && (!index || !value))) return fail(TOK_EINVAL, "null argument");
+  auto al = [](const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+  if (!al(x, 16) || !al(r, 16) || !al(clip_offsets, 8) || !al(rs_ws, 4) || !al(index, 4) || !al(value, 4))
+    return fail(TOK_EINVAL, "x and r must be 16-byte, clip_offsets 8-byte, rs_ws, index and value 4-byte aligned");
+  if (T2 < 1 || H2 < 1 || W2 < 1 || N < 1 || N > 65535 || (long long)N * 3 * (4 * H2) * (4 * W2) >= 0xffffffffLL)
+    return fail(TOK_ESHAPE, "bad latent shape, or N H W 3 >= 2^32");
+  const int T = 4 * (T2 - 1) + 1, H = 4 * H2, W = 4 * W2;
+  if (rs_ws_bytes < residual_ws_bytes(N, H, W)) return fail(TOK_EWORKSPACE, "residual workspace too small");
+  if (m->prec == P_F32) {
+    // (the fp32 last layer does not walk frames: decode, then the standalone residual pass)
+    TOK_TRY(decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, nullptr));
+    TOK_HIP(launch_residual(x, xhat, N, T, H, W, theta, r, index, value, (long long)capacity,
+                            reinterpret_cast<unsigned long long*>(clip_offsets), rs_ws, s));
+    return TOK_OK;
+  }
+  const ResAcc ra{x, r, T};
+  TOK_TRY(decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, nullptr, &ra));
+  TOK_HIP(launch_residual_sums(r, N, T, H, W, theta, index, value, (long long)capacity,
+                               reinterpret_cast<unsigned long long*>(clip_offsets), rs_ws, s));
+  return TOK_OK;
 }
 
 }  // extern "C"

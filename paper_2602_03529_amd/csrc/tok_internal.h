@@ -121,6 +121,15 @@ struct ConvLaunch {
   // (float NDHWC, blend_Tp frames per clip); null for none.
   const float* blend_prev;
   int blend_Tp, blend_n;
+  // Frame-walking last layer only: pixel-residual sums (Sec. 4.3, Eq. 4) of
+  // the frames written, sum_t (x_t / 127.5 - 1 - x_hat_t) per (n, h, w,
+  // colour) in frame order (x_hat_t as stored, i.e. after blending), in fp32
+  // into rs_sum (float (N, Ho, Wo, 3)); they start from rs_sum's contents
+  // when go0 > 0 (a later chunk of the clip), else from 0.  rs_x is the
+  // uint8 source (N, rs_T, Ho, Wo, 3), indexed by global frame.  Null: none.
+  const uint8_t* rs_x;
+  float* rs_sum;
+  int rs_T;
 };
 
 // Tile geometry per mode (output rows x cols per workgroup).
@@ -210,6 +219,10 @@ size_t residual_ws_bytes(int N, int H, int W);
 hipError_t launch_residual(const uint8_t* x, const float* xhat, int N, int T, int H, int W, float theta, float* rs,
                            uint32_t* index, float* value, long long capacity, unsigned long long* clip_off,
                            void* ws, hipStream_t s);
+// The same from sums rs[n, h, w, c] = sum_t (x_t / 127.5 - 1 - x_hat_t) the
+// decoder's last layer accumulated (rs becomes the thresholded mean).
+hipError_t launch_residual_sums(float* rs, int N, int T, int H, int W, float theta, uint32_t* index, float* value,
+                                long long capacity, unsigned long long* clip_off, void* ws, hipStream_t s);
 hipError_t launch_residual_apply(const float* rs, float* xhat, int N, int T, int H, int W, hipStream_t s);
 hipError_t launch_blend(const float* prev, int Tp, float* cur, int N, int T, int H, int W, int nb, hipStream_t s);
 hipError_t launch_similarity_drop(float* codes, uint8_t* keep, int N, int T2, int H2, int W2, long long D, void* ws,

@@ -135,6 +135,33 @@ class TokModel:
                 _stream(codes.device)))
         return xh
 
+    def decode_residual(self, codes: torch.Tensor, x: torch.Tensor, theta: float, capacity=None, out=None, ws=None):
+        """decode, then the pixel residual layer (Sec. 4.3, Eq. 4) of source
+        clips x uint8 (N,T,H,W,3) against the decoded clips, with the residual
+        sums formed by the decoder's last conv as it writes each frame:
+        dict(xhat, r (N,H,W,3), index, value, clip_offsets [N+1]), equal to
+        decode then residual_compress."""
+        N, T2, H2, W2, _ = codes.shape
+        _need(codes, torch.float32, (N, T2, H2, W2, 6), "codes")
+        T, H, W = 4 * (T2 - 1) + 1, 4 * H2, 4 * W2
+        _need(x, torch.uint8, (N, T, H, W, 3), "x")
+        dev = codes.device
+        xh = out if out is not None else torch.empty((N, T, H, W, 3), dtype=torch.float32, device=dev)
+        if ws is None:
+            ws = self.workspace(N, T, H, W, L.TOK_WS_DECODE if self.precision == "fp8" else L.TOK_WS_ROUNDTRIP)
+        cap = N * H * W * 3 if capacity is None else int(capacity)
+        r = torch.empty((N, H, W, 3), dtype=torch.float32, device=dev)
+        index = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        value = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        co = torch.empty(N + 1, dtype=torch.uint64, device=dev)
+        b = C.c_size_t()
+        L.check("tok_residual_workspace_size", self.lib.tok_residual_workspace_size(N, H, W, C.byref(b)))
+        rws = torch.empty(int(b.value), dtype=torch.uint8, device=dev)
+        L.check("tok_decode_residual", self.lib.tok_decode_residual(
+            self.handle, _ptr(codes), N, T2, H2, W2, _ptr(x), float(theta), _ptr(xh), _ptr(r), _ptr(index),
+            _ptr(value), cap, _ptr(co), _ptr(ws), ws.numel(), _ptr(rws), rws.numel(), _stream(dev)))
+        return dict(xhat=xh, r=r, index=index, value=value, clip_offsets=co)
+
 
     # ---- training step (tok_train_forward / tok_backward) -----------------
     def set_weights(self, w: torch.Tensor):

@@ -316,3 +316,35 @@ def test_fused_blend_errors(tk, f32_model):
         f32_model.decode(codes, prev=torch.zeros((1, 1, 16, 16, 3), device="cuda"), blend_n=2)
     with pytest.raises(TokError):
         f32_model.decode(codes, prev=torch.zeros((1, 9, 16, 16, 3), device="cuda"), blend_n=6)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "fp8"])
+def test_fused_residual_equals_decode_then_residual(tk, prec):
+    """decode_residual (the residual sums formed by the decoder's last conv as
+    it writes each frame, Sec. 4.3 Eq. 4) equals decode followed by
+    residual_compress bit for bit: x_hat, the thresholded mean r, the clip
+    offsets and the sparse list; for bf16 / f32 also when the decode runs in
+    temporal chunks (the sums carried from chunk to chunk)."""
+    import synth
+    from tests import gpu_common as G
+    m = tk.TokModel(synth.flatten_weights(G.weights(True)), prec)
+    N, T2, H2, W2 = 2, 3, 12, 20
+    T, H, W = 4 * (T2 - 1) + 1, 4 * H2, 4 * W2
+    codes = torch.from_numpy(uniform_codes(70, N, T2, H2, W2)).cuda()
+    x = torch.from_numpy(np.random.default_rng(71).integers(0, 256, (N, T, H, W, 3), dtype=np.uint8)).cuda()
+    theta = 0.05
+    plain = m.decode(codes)
+    ref = tk.residual_compress(x, plain, theta)
+    runs = [None]
+    if prec != "fp8":
+        runs.append(torch.empty(m.workspace_size(N, T, H, W, stream=True), dtype=torch.uint8, device="cuda"))
+    for ws in runs:
+        got = m.decode_residual(codes, x, theta, ws=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(got["xhat"], plain)
+        assert torch.equal(got["r"], ref["r"])
+        assert torch.equal(got["clip_offsets"], ref["clip_offsets"])
+        total = int(ref["clip_offsets"][-1].item())
+        assert 0 < total < N * H * W * 3
+        assert torch.equal(got["index"][:total], ref["index"][:total])
+        assert torch.equal(got["value"][:total], ref["value"][:total])
