@@ -270,12 +270,12 @@ tok_status tok_decode_blend(tok_model* model, const float* codes, int N, int T2,
 
 /* tok_decode followed by tok_residual_compress of the decoded clip (Sec. 4.3,
  * Eq. 4; the averaging window is the clip's T = 4(T2-1)+1 frames), with the
- * residual sums fused into C_out (bf16 and fp8 models): as the last layer
- * writes each frame of x_hat it adds x_t/127.5 - 1 - x_hat_t, in fp32 and in
- * frame order, into r, so the separate pass over the T frames of x and x_hat
- * is not needed; then r becomes the thresholded mean and its non-zero
- * entries are listed.  Results equal tok_decode then tok_residual_compress
- * bit for bit (fp32 models run exactly that).  x: uint8 (N,T,4 H2,4 W2,3)
+ * residual sums fused into C_out for bf16 models: as the last layer writes
+ * each frame of x_hat it adds x_t/127.5 - 1 - x_hat_t, in fp32 and in frame
+ * order, into r, so the separate pass over the T frames of x and x_hat is
+ * not needed; then r becomes the thresholded mean and its non-zero entries
+ * are listed.  Results equal tok_decode then tok_residual_compress bit for
+ * bit (fp32 and fp8 models run exactly that).  x: uint8 (N,T,4 H2,4 W2,3)
  * source clips (device, 16-byte aligned); xhat, ws, ws_bytes as tok_decode;
  * r, index, value, capacity, clip_offsets as tok_residual_compress; rs_ws:
  * device scratch of tok_residual_workspace_size(N, 4 H2, 4 W2) bytes.

@@ -1415,6 +1415,7 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
   for (int m = 0; m < 8; ++m) o0[m] = o1[m] = o2[m] = init;
   // pixel-residual sums of this lane's 8 positions (colour g4), carried over
   // from the clip's earlier chunks
+  static_assert(!RS || !F8, "residual sums: bf16");
   const bool rs_on = RS && g4 < 3;
   float rsum[8];
 #pragma unroll
@@ -1427,6 +1428,24 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
 
   const int f_first = max(a.go0 - 2, 0), f_end = a.go0 + a.To;
   for (int fg = f_first; fg < f_end; ++fg) {
+    // residual: the tile's source bytes of this frame, 8 rows x 192 bytes =
+    // 384 dwords (row r, dword q: bytes 12 q .. of columns w0 + ..), loaded
+    // before its stages so that they arrive while the halo transfers are
+    // awaited; rows past the frame are skipped, bytes past the frame's end
+    // read as zeros (columns past Wo are never used)
+    constexpr int XDW = 8 * 48;
+    uint32_t xd[2] = {0u, 0u};
+    if (RS && fg >= a.go0) {
+      const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t*>(a.rs_x + ((size_t)n * a.rs_T + fg) * plane_out * 3), (short)0, (int)(plane_out * 3),
+          0x00020000);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int dq = tid + k * kThreads, r = dq / 48, q = dq % 48;
+        if (dq < XDW && h0 + r < a.Ho)
+          xd[k] = __builtin_amdgcn_raw_buffer_load_b32(xr, (int)((((h0 + r) * a.Wo + w0) * 3) + 4 * q), 0, 0);
+      }
+    }
     f32x4 d[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) d[m] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -1510,6 +1529,21 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
           }
       }
     }
+    // residual: the source bytes through the (now unused) halo buffer; lane
+    // (l16, g4) takes colour g4 of its 8 positions (byte m & 3 of xv[m >> 2])
+    uint32_t xv[2] = {0u, 0u};
+    if (RS && fg >= a.go0) {
+      __syncthreads();  // every wave is done reading this frame's halo
+      uint32_t* lx = reinterpret_cast<uint32_t*>(lds_h);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (tid + k * kThreads < XDW) lx[tid + k * kThreads] = xd[k];
+      __syncthreads();
+      const uint8_t* lb = reinterpret_cast<const uint8_t*>(lds_h);
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        xv[m >> 2] |= (uint32_t)lb[(2 * wave + (m >> 2)) * 192 + ((m & 3) * 16 + l16) * 3 + min(g4, 2)] << (8 * (m & 3));
+    }
     // taps of frame fg: d[m][kt] belongs to output frame fg + 2 - kt (frame 0: to
     // every output frame whose clamped tap reads it)
 #pragma unroll
@@ -1541,10 +1575,7 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
         }
         reinterpret_cast<float*>(a.out)[(((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3 +
                                         g4] = y;
-        if (rs_on) {
-          const uint32_t u = a.rs_x[(((size_t)n * a.rs_T + fg) * plane_out + (size_t)oh * a.Wo + ow) * 3 + g4];
-          rsum[m] += ((float)u / 127.5f - 1.0f) - y;
-        }
+        if (rs_on) rsum[m] += ((float)((xv[m >> 2] >> (8 * (m & 3))) & 255u) / 127.5f - 1.0f) - y;
       }
     }
 #pragma unroll
@@ -1574,8 +1605,13 @@ hipError_t launch_rgb_walk(const ConvLaunch& a, hipStream_t s) {
   if (a.rs_sum && (!a.rs_x || a.go0 + a.To > a.rs_T)) return hipErrorInvalidValue;  // residual sums: source frames
   const long long nb = (long long)a.N * a.tiles_h * a.tiles_w;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (a.rs_sum) hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, true>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, false>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  if (a.rs_sum) {
+    // (residual sums: bf16 only; the fp8 variant measured slower than the separate pass)
+    if constexpr (PREC != P_BF16) return hipErrorInvalidValue;
+    else hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, true>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, false>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -459,7 +459,7 @@ Fp8Plan make_fp8_plan(const Dims& d) {
 }
 
 tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xhat, void* ws, size_t ws_bytes,
-                      hipStream_t s, const Blend* blend, const ResAcc* racc) {
+                      hipStream_t s, const Blend* blend) {
   const Fp8Plan p = make_fp8_plan(d);
   if (p.total > ws_bytes)
     return fail(TOK_EWORKSPACE, "fp8 decode workspace needs " + std::to_string(p.total) + " bytes");
@@ -504,7 +504,7 @@ tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xh
                    s, u8(p.Ssc), u8(p.Csc)));
   }
   return conv(m, L_CONV_OUT, CM_S1, at(p.C), IN_ACT, N, w0, H, W, 64, xhat, OUT_RGB32, w0, H, W, nullptr, nullptr, s,
-              u8(p.Csc), nullptr, blend, racc);
+              u8(p.Csc), nullptr, blend);
 }
 
 }  // namespace
@@ -802,7 +802,7 @@ tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, 
   if (blend && (!blend->prev || blend->n < 1 || blend->n > d.T || blend->n > blend->Tp ||
                 (reinterpret_cast<uintptr_t>(blend->prev) & 3)))
     return fail(TOK_EINVAL, "blend needs a 4-byte aligned prev and 1 <= n <= T, T_prev");
-  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend, racc);
+  if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend);
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))
     return fail(TOK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes");
@@ -862,8 +862,9 @@ tok_status tok_decode_residual(tok_model* m, const float* codes, int N, int T2, 
     return fail(TOK_ESHAPE, "bad latent shape, or N H W 3 >= 2^32");
   const int T = 4 * (T2 - 1) + 1, H = 4 * H2, W = 4 * W2;
   if (rs_ws_bytes < residual_ws_bytes(N, H, W)) return fail(TOK_EWORKSPACE, "residual workspace too small");
-  if (m->prec == P_F32) {
-    // (the fp32 last layer does not walk frames: decode, then the standalone residual pass)
+  if (m->prec != P_BF16) {
+    // (the fp32 last layer does not walk frames, and the fp8 walk with the sums measured slower than
+    // decode then the standalone pass: that is what these models run)
     TOK_TRY(decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, nullptr));
     TOK_HIP(launch_residual(x, xhat, N, T, H, W, theta, r, index, value, (long long)capacity,
                             reinterpret_cast<unsigned long long*>(clip_offsets), rs_ws, s));

@@ -320,11 +320,12 @@ def test_fused_blend_errors(tk, f32_model):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16", "fp8"])
 def test_fused_residual_equals_decode_then_residual(tk, prec):
-    """decode_residual (the residual sums formed by the decoder's last conv as
-    it writes each frame, Sec. 4.3 Eq. 4) equals decode followed by
-    residual_compress bit for bit: x_hat, the thresholded mean r, the clip
-    offsets and the sparse list; for bf16 / f32 also when the decode runs in
-    temporal chunks (the sums carried from chunk to chunk)."""
+    """decode_residual equals decode followed by residual_compress bit for
+    bit: x_hat, the thresholded mean r, the clip offsets and the sparse list.
+    bf16: the residual sums are formed by the decoder's last conv as it writes
+    each frame (Sec. 4.3 Eq. 4), also when the decode runs in temporal chunks
+    (the sums carried from chunk to chunk); f32 / fp8 run decode then the
+    separate pass."""
     import synth
     from tests import gpu_common as G
     m = tk.TokModel(synth.flatten_weights(G.weights(True)), prec)
