@@ -1,4 +1,4 @@
-"""Streaming workload driver for the tokenizer server (tok_server_*).
+"""Streaming load generator for the tokenizer server (tok_server_*).
 
 Clips arrive by a Poisson process and are submitted at their wall-clock
 arrival times; the native server admits them as stream slots and arena
