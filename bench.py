@@ -401,14 +401,30 @@ def coding_leg(tok, x, xhat, codes, idx, args, model=None):
     out["residual_compress"] = entry(ms, px * T * 5 + px * 4 + nnz * 8, theta=theta, nonzero=nnz,
                                      note="untrained stand-in weights: the residual is dense")
     if model is not None:
+        # per-launch HIP events of the library's profiler: the last conv with
+        # and without the residual sums, and the residual tail (threshold,
+        # scan, compaction)
         xh2 = torch.empty_like(xhat)
-        ms_dec = timed_op(lambda: model.decode(codes, out=xh2), iters=5)
-        ms_fused = timed_op(lambda: model.decode_residual(codes, x, theta, out=xh2), iters=5)
+
+        def layer_us(fn, iters=5):
+            fn()
+            torch.cuda.synchronize()
+            prof = tok.Profile(model)
+            prof.__enter__()
+            for _ in range(iters):
+                fn()
+            torch.cuda.synchronize()
+            prof.__exit__(None, None, None)
+            return {k: prof.ms[k] / prof.count[k] * 1e3 for k in ("dec.conv_out", "dec.residual") if prof.count[k]}
+        plain = layer_us(lambda: model.decode(codes, out=xh2))
+        fused = layer_us(lambda: model.decode_residual(codes, x, theta, out=xh2))
+        added = fused["dec.conv_out"] - plain["dec.conv_out"] + fused["dec.residual"]
         out["decode_residual_fused"] = dict(
-            decode_us=round(ms_dec * 1e3, 1), decode_residual_us=round(ms_fused * 1e3, 1),
-            added_us=round((ms_fused - ms_dec) * 1e3, 1),
+            conv_out_us=round(plain["dec.conv_out"], 1), conv_out_with_sums_us=round(fused["dec.conv_out"], 1),
+            tail_us=round(fused["dec.residual"], 1), residual_us=round(added, 1),
             separate_residual_compress_us=out["residual_compress"]["us_per_call"],
-            note="residual sums formed by the last conv while it writes each frame, then threshold and compaction")
+            note="residual sums formed by the last conv while it writes each frame; tail = threshold, scan, "
+                 "compaction; residual_us = the conv's extra time + tail")
         del xh2
     r = res["r"]
     ms = timed_op(lambda: tok.residual_apply(r, xhat))

@@ -303,7 +303,9 @@ tok_status tok_decode(tok_model* model, const float* codes, int N, int T2, int H
  * and for tok_train_forward / tok_backward: 18 adjoint (input-gradient)
  * convolutions, 19 weight-gradient kernels, 20 GroupNorm+SiLU backward,
  * 21 other backward kernels, 22 similarity-based token selection (tok_encode
- * with TOK_DROP_SIMILARITY); tok_kernel_name(k) names them.
+ * with TOK_DROP_SIMILARITY), 23 the residual layer of tok_decode_residual
+ * (threshold, scan and compaction; for fp32 / fp8 models the whole separate
+ * pass); tok_kernel_name(k) names them.
  * Profiling allocates events and is meant for measurement runs; do not
  * profile one model from several host threads at once. */
 tok_status tok_profile_begin(tok_model* model);

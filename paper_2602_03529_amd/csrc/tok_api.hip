@@ -174,7 +174,7 @@ const char* kKernelNames[K_IDS] = {
     "enc.conv_in", "enc.rb1.a", "enc.rb1.b", "enc.rb2.a", "enc.rb2.b", "enc.down1", "enc.down2",
     "enc.proj+fsq+drop", "dec.proj_in", "dec.up2", "dec.up1", "dec.rb1.a", "dec.rb1.b", "dec.rb2.a",
     "dec.rb2.b", "dec.conv_out", "gn_finalize", "gn_silu", "bwd.dgrad", "bwd.wgrad", "bwd.gn_silu",
-    "bwd.other", "select.similarity"};
+    "bwd.other", "select.similarity", "dec.residual"};
 
 // Conv launch: reads the whole input buffer `iw` (its frames are addressed
 // through their global numbers) and writes the window `ow` of the output.
@@ -866,12 +866,14 @@ tok_status tok_decode_residual(tok_model* m, const float* codes, int N, int T2, 
     // (the fp32 last layer does not walk frames, and the fp8 walk with the sums measured slower than
     // decode then the standalone pass: that is what these models run)
     TOK_TRY(decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, nullptr));
+    Timed tm(m, K_RESID, s);
     TOK_HIP(launch_residual(x, xhat, N, T, H, W, theta, r, index, value, (long long)capacity,
                             reinterpret_cast<unsigned long long*>(clip_offsets), rs_ws, s));
     return TOK_OK;
   }
   const ResAcc ra{x, r, T};
   TOK_TRY(decode_impl(m, codes, N, T2, H2, W2, xhat, ws, ws_bytes, s, nullptr, &ra));
+  Timed tm(m, K_RESID, s);
   TOK_HIP(launch_residual_sums(r, N, T, H, W, theta, index, value, (long long)capacity,
                                reinterpret_cast<unsigned long long*>(clip_offsets), rs_ws, s));
   return TOK_OK;

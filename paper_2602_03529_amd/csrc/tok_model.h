@@ -72,7 +72,7 @@ FsqConst make_fsq_const();
 // Kernel ids of the per-launch profile (tok_profile_end).
 enum KernelId {
   K_GN_FINAL = 16, K_GN_ACT = 17, K_DGRAD = 18, K_WGRAD = 19, K_GN_BWD = 20, K_BWD_MISC = 21, K_SELECT = 22,
-  K_IDS = 23
+  K_RESID = 23, K_IDS = 24
 };
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }

@@ -572,7 +572,7 @@ class FsqSTEFn(torch.autograd.Function):
         return fsq_ste_bwd(z, gc.contiguous(), keep), None
 
 
-KERNEL_IDS = 23
+KERNEL_IDS = 24
 
 
 class Profile:
