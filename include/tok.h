@@ -262,8 +262,10 @@ tok_status tok_gop_blend(const float* prev, int T_prev, float* xhat, int N, int 
  * float32, device), the previous GoP's reconstruction, so a stream of GoPs
  * is decoded and smoothed in one pass per GoP (overlapped-GoP streaming keeps
  * the last n frames of each output as the next call's prev, T_prev = n).
- * prev must not overlap xhat.  Errors as tok_decode, plus TOK_EINVAL for a
- * null prev or n outside 1..min(T, T_prev). */
+ * prev must not overlap xhat.  fp8 models blend in a separate pass after the
+ * last layer (same arithmetic as tok_gop_blend) and need prev and xhat
+ * 16-byte aligned.  Errors as tok_decode, plus TOK_EINVAL for a null or
+ * misaligned prev or n outside 1..min(T, T_prev). */
 tok_status tok_decode_blend(tok_model* model, const float* codes, int N, int T2, int H2, int W2,
                             const float* prev, int T_prev, int n, float* xhat, void* ws,
                             size_t ws_bytes, hipStream_t stream);

@@ -1350,7 +1350,7 @@ hipError_t launch_one(const ConvLaunch& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int kWalkHW = 66, kWalkHalo = 10 * kWalkHW, kWalkHQ = kWalkHalo * 4;
 
-template <int PREC, bool RS>
+template <int PREC, bool RS, bool BL>
 __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a) {
   constexpr bool F8 = PREC == P_FP8;
   constexpr int NCK = F8 ? 1 : 2;  // input chunks (64 channels)
@@ -1415,7 +1415,7 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
   for (int m = 0; m < 8; ++m) o0[m] = o1[m] = o2[m] = init;
   // pixel-residual sums of this lane's 8 positions (colour g4), carried over
   // from the clip's earlier chunks
-  static_assert(!RS || !F8, "residual sums: bf16");
+  static_assert(!(RS || BL) || !F8, "residual sums and blending: bf16");
   const bool rs_on = RS && g4 < 3;
   float rsum[8];
 #pragma unroll
@@ -1435,6 +1435,26 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
     // read as zeros (columns past Wo are never used)
     constexpr int XDW = 8 * 48;
     uint32_t xd[2] = {0u, 0u};
+    // blending: the tile's pixels of the previous GoP's frame that output
+    // frame fg is blended with, 8 rows x 192 floats, likewise (rows past the
+    // frame skipped, floats past its end read as zeros)
+    constexpr int PDW = 8 * 192, PK = PDW / kThreads;
+    const bool bl_f = BL && fg >= a.go0 && fg < a.blend_n;
+    float pd[BL ? PK : 1];
+#pragma unroll
+    for (int k = 0; k < (BL ? PK : 1); ++k) pd[k] = 0.f;
+    if (bl_f) {
+      const __amdgpu_buffer_rsrc_t pr = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(a.blend_prev + ((size_t)n * a.blend_Tp + (a.blend_Tp - a.blend_n + fg)) * plane_out * 3),
+          (short)0, (int)(plane_out * 12), 0x00020000);
+#pragma unroll
+      for (int k = 0; k < (BL ? PK : 1); ++k) {
+        const int dq = tid + k * kThreads, r = dq / 192, q = dq % 192;
+        if (h0 + r < a.Ho)
+          pd[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                pr, (int)(((((h0 + r) * a.Wo + w0) * 3) + q) * 4), 0, 0));
+      }
+    }
     if (RS && fg >= a.go0) {
       const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<uint8_t*>(a.rs_x + ((size_t)n * a.rs_T + fg) * plane_out * 3), (short)0, (int)(plane_out * 3),
@@ -1532,17 +1552,28 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
     // residual: the source bytes through the (now unused) halo buffer; lane
     // (l16, g4) takes colour g4 of its 8 positions (byte m & 3 of xv[m >> 2])
     uint32_t xv[2] = {0u, 0u};
-    if (RS && fg >= a.go0) {
+    float pv[BL ? 8 : 1];
+    if ((RS && fg >= a.go0) || bl_f) {
       __syncthreads();  // every wave is done reading this frame's halo
       uint32_t* lx = reinterpret_cast<uint32_t*>(lds_h);
+      float* lp = reinterpret_cast<float*>(lds_h) + 512;  // (after the residual's 1536 bytes)
+      if (RS) {
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
-        if (tid + k * kThreads < XDW) lx[tid + k * kThreads] = xd[k];
+        for (int k = 0; k < 2; ++k)
+          if (tid + k * kThreads < XDW) lx[tid + k * kThreads] = xd[k];
+      }
+      if (BL) {
+#pragma unroll
+        for (int k = 0; k < (BL ? PK : 1); ++k) lp[tid + k * kThreads] = pd[k];
+      }
       __syncthreads();
       const uint8_t* lb = reinterpret_cast<const uint8_t*>(lds_h);
 #pragma unroll
-      for (int m = 0; m < 8; ++m)
-        xv[m >> 2] |= (uint32_t)lb[(2 * wave + (m >> 2)) * 192 + ((m & 3) * 16 + l16) * 3 + min(g4, 2)] << (8 * (m & 3));
+      for (int m = 0; m < 8; ++m) {
+        const int e = (2 * wave + (m >> 2)) * 192 + ((m & 3) * 16 + l16) * 3 + min(g4, 2);
+        if (RS) xv[m >> 2] |= (uint32_t)lb[e] << (8 * (m & 3));
+        if constexpr (BL) pv[m] = lp[e];
+      }
     }
     // taps of frame fg: d[m][kt] belongs to output frame fg + 2 - kt (frame 0: to
     // every output frame whose clamped tap reads it)
@@ -1566,12 +1597,12 @@ __global__ void __launch_bounds__(kThreads, 3) conv_rgb_walk_kernel(ConvLaunch a
         const int oh = h0 + 2 * wave + (m >> 2), ow = w0 + (m & 3) * 16 + l16;
         if (oh >= a.Ho || ow >= a.Wo) continue;
         float y = F8 ? o0[m] * wsc + bias : o0[m];
-        if (a.blend_prev != nullptr && fg < a.blend_n) {
-          // frame i = fg + 1 of the GoP: a_i prev[Tp - n + i] + (1 - a_i) x_hat, a_i = (n - i) / n
-          const float al = (float)(a.blend_n - (fg + 1)) / (float)a.blend_n, be = 1.0f - al;
-          const float pv = a.blend_prev[(((size_t)n * a.blend_Tp + (a.blend_Tp - a.blend_n + fg)) * plane_out +
-                                         (size_t)oh * a.Wo + ow) * 3 + g4];
-          y = al * pv + be * y;
+        if constexpr (BL) {
+          if (fg < a.blend_n) {
+            // frame i = fg + 1 of the GoP: a_i prev[Tp - n + i] + (1 - a_i) x_hat, a_i = (n - i) / n
+            const float al = (float)(a.blend_n - (fg + 1)) / (float)a.blend_n, be = 1.0f - al;
+            y = al * pv[m] + be * y;
+          }
         }
         reinterpret_cast<float*>(a.out)[(((size_t)n * a.To_buf + a.out_f0 + to) * plane_out + (size_t)oh * a.Wo + ow) * 3 +
                                         g4] = y;
@@ -1606,11 +1637,18 @@ hipError_t launch_rgb_walk(const ConvLaunch& a, hipStream_t s) {
   const long long nb = (long long)a.N * a.tiles_h * a.tiles_w;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
   if (a.rs_sum) {
-    // (residual sums: bf16 only; the fp8 variant measured slower than the separate pass)
+    // (residual sums: bf16 only, and not with blending; the fp8 variant measured slower than the separate pass)
     if constexpr (PREC != P_BF16) return hipErrorInvalidValue;
-    else hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, true>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+    else {
+      if (a.blend_prev) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, true, false>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+    }
+  } else if (a.blend_prev) {
+    // (blending: bf16 only; the fp8 variant measured slower than the separate blend pass)
+    if constexpr (PREC != P_BF16) return hipErrorInvalidValue;
+    else hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, false, true>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
   } else {
-    hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, false>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((conv_rgb_walk_kernel<PREC, false, false>), dim3((unsigned)nb), dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -503,8 +503,11 @@ tok_status decode_fp8(tok_model* m, const float* codes, const Dims& d, float* xh
       TOK_TRY(conv(m, la + 1, CM_S1, at(p.S), IN_ACT, N, w0, H, W, 64, at(p.C), OUT_FP8, w0, H, W, at(p.A), nullptr,
                    s, u8(p.Ssc), u8(p.Csc)));
   }
-  return conv(m, L_CONV_OUT, CM_S1, at(p.C), IN_ACT, N, w0, H, W, 64, xhat, OUT_RGB32, w0, H, W, nullptr, nullptr, s,
-              u8(p.Csc), nullptr, blend);
+  TOK_TRY(conv(m, L_CONV_OUT, CM_S1, at(p.C), IN_ACT, N, w0, H, W, 64, xhat, OUT_RGB32, w0, H, W, nullptr, nullptr, s,
+               u8(p.Csc)));
+  // GoP blending as its own pass after the fp8 last layer (the walk with the blend measured slower)
+  if (blend) TOK_HIP(launch_blend(blend->prev, blend->Tp, xhat, N, T, H, W, blend->n, s));
+  return TOK_OK;
 }
 
 }  // namespace
@@ -802,6 +805,9 @@ tok_status decode_impl(tok_model* m, const float* codes, int N, int T2, int H2, 
   if (blend && (!blend->prev || blend->n < 1 || blend->n > d.T || blend->n > blend->Tp ||
                 (reinterpret_cast<uintptr_t>(blend->prev) & 3)))
     return fail(TOK_EINVAL, "blend needs a 4-byte aligned prev and 1 <= n <= T, T_prev");
+  if (blend && m->prec == P_FP8 &&
+      ((reinterpret_cast<uintptr_t>(blend->prev) & 15) || (reinterpret_cast<uintptr_t>(xhat) & 15)))
+    return fail(TOK_EINVAL, "fp8 blend (a separate pass) needs 16-byte aligned prev and xhat");
   if (m->prec == P_FP8) return decode_fp8(m, codes, d, xhat, ws, ws_bytes, s, blend);
   Plan p;
   if (!choose_chunk(d, m->prec, ws_bytes, &p))
