@@ -349,3 +349,24 @@ def test_fused_residual_equals_decode_then_residual(tk, prec):
         assert 0 < total < N * H * W * 3
         assert torch.equal(got["index"][:total], ref["index"][:total])
         assert torch.equal(got["value"][:total], ref["value"][:total])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_fused_blend_chunked_equals_whole_clip(tk, prec):
+    """A blended decode run in temporal chunks (one latent frame at a time:
+    blended frame 1 is written by the second chunk) equals the whole-clip
+    blended decode bit for bit."""
+    import synth
+    from tests import gpu_common as G
+    m = tk.TokModel(synth.flatten_weights(G.weights(True)), prec)
+    N, T2, H2, W2 = 2, 3, 10, 20
+    T, H, W = 4 * (T2 - 1) + 1, 4 * H2, 4 * W2
+    codes = torch.from_numpy(uniform_codes(80, N, T2, H2, W2)).cuda()
+    prev = torch.from_numpy(np.random.default_rng(81).normal(0, 1, (N, 3, H, W, 3)).astype(np.float32)).cuda()
+    ws = torch.empty(m.workspace_size(N, T, H, W, stream=True), dtype=torch.uint8, device="cuda")
+    whole = m.decode(codes, prev=prev, blend_n=3)
+    chunked = m.decode(codes, prev=prev, blend_n=3, ws=ws)
+    plain = m.decode(codes)
+    torch.cuda.synchronize()
+    assert torch.equal(whole, chunked)
+    assert torch.equal(whole[:, 3:], plain[:, 3:]) and not torch.equal(whole[:, 1:3], plain[:, 1:3])
